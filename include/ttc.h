@@ -1,0 +1,277 @@
+/*
+ * ttc.h — C ABI of the MI355X (gfx950) library for tensor contraction
+ * products computed directly on Tensor-Train (TT) cores.
+ *
+ * Method: Kisil, Calvi, Konstantinidis, Xu, Mandic, "Reducing Computational
+ * Complexity of Tensor Contractions via Tensor-Train Networks"
+ * (arXiv 2109.00626).  Section III contracts two tensors through their TT
+ * cores (Algorithm 2); the first step of that contraction is the product of
+ * the two first cores, K = A_x^T A_y.  This library generalises that step to
+ * the interface sweep over a block of shared modes, and adds mode-n products
+ * (Def. 5) and TT-matrix products on cores.
+ *
+ * Conventions (every call):
+ *  - A TT of order N has mode sizes I[0..N-1] and ranks R[0..N] with
+ *    R[0] = R[N] = 1 (Def. 7, eq. (9)).  Core k is one device buffer, a
+ *    row-major (R[k], I[k], R[k+1]) array.  Modes are 0-based here; the
+ *    paper counts from 1.
+ *  - A TT-matrix (MPO) core k is a row-major (R[k], I[k], J[k], R[k+1]) array.
+ *    Its dense matrix W[i, j] = prod_k W^(k)[:, i_k, j_k, :], with the row
+ *    index i and column index j little-endian over (i_0..i_{N-1}) and
+ *    (j_0..j_{N-1}), first index fastest (Def. 2, eq. (2) first line; Def. 3).
+ *  - Dense multi-way outputs are ordinary row-major arrays indexed
+ *    (i_0, ..., i_{n-1}); only flattened vectors (TT-matrix rows and
+ *    columns, batch rows) use the little-endian index.
+ *  - Pointers named d_* are device pointers; descriptor arrays (modes, ranks,
+ *    core pointer lists) live in host memory and are read during the call
+ *    only.  The caller owns every buffer.  The library never allocates on
+ *    these calls: scratch memory comes from the caller as (d_ws, ws_bytes),
+ *    sized by the matching *_query call.  Plans of the batched interface are
+ *    the only library-owned objects.
+ *  - `stream` is a hipStream_t passed as void* (0 = the null stream).  Calls
+ *    are asynchronous on that stream and never synchronise the host, except
+ *    tt_batch_plan_create.
+ *  - Errors: every call validates all arguments on the host before any
+ *    launch.  On error it returns a non-zero ttc_status, writes no output
+ *    byte, and sets a thread-local message readable with ttc_last_error().
+ *    No C++ exception crosses this interface.
+ *  - Results are deterministic run to run (no floating-point atomics).
+ */
+#ifndef TTC_H
+#define TTC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TTC_ABI_VERSION 1
+#define TTC_MAX_ORDER 32 /* largest TT order accepted by single-pair calls */
+
+typedef enum {
+  TTC_OK = 0,
+  TTC_ERR_NULL = 1,        /* a required pointer is NULL                         */
+  TTC_ERR_SHAPE = 2,       /* mode sizes differ / do not match an operand        */
+  TTC_ERR_RANK = 3,        /* boundary rank != 1, rank < 1, or rank mismatch     */
+  TTC_ERR_MODE = 4,        /* mode index out of range or repeated                */
+  TTC_ERR_DTYPE = 5,       /* dtype not supported or operands disagree           */
+  TTC_ERR_UNSUPPORTED = 6, /* valid request this GPU path does not implement     */
+  TTC_ERR_WORKSPACE = 7,   /* workspace smaller than the *_query size            */
+  TTC_ERR_HIP = 8          /* a HIP runtime call or launch failed                */
+} ttc_status;
+
+typedef enum { TTC_F64 = 0, TTC_F32 = 1, TTC_BF16 = 2 } ttc_dtype;
+
+/* Arithmetic precision.  AUTO: FP64 for FP64 inputs; FP32 interfaces with
+ * FP32 accumulation for FP32 and BF16 inputs.  BF16: operands rounded to
+ * BF16 (round to nearest even) on the matrix cores, FP32 accumulation.
+ * Final scalars of inner products are always accumulated in FP64. */
+typedef enum { TTC_PREC_AUTO = 0, TTC_PREC_F64 = 1, TTC_PREC_F32 = 2, TTC_PREC_BF16 = 3 } ttc_prec;
+
+/* Output form of a partial contraction.
+ *  JUNCTION: the matrix K joining X's free cores to Y's free cores (the K
+ *            node of the paper's Fig. 3); free cores are not copied.
+ *  NATURAL_TT: one TT over X's free modes then Y's (the mode order of
+ *            eq. (8) and Algorithm 2's last step); the carried bond of K is
+ *            lifted through the cores with merged index (own bond)*Q + q.
+ *  DENSE:    the dense row-major result (small cases). */
+typedef enum { TTC_JUNCTION = 0, TTC_NATURAL_TT = 1, TTC_DENSE = 2 } ttc_form;
+
+/* Schedule of a TT-matrix x dense-batch product.  CORES: contract the batch
+ * with one core at a time.  DENSE: rebuild the dense matrix from the cores,
+ * then one matrix product.  AUTO picks the smaller FLOP count. */
+typedef enum { TTC_SCHED_AUTO = 0, TTC_SCHED_CORES = 1, TTC_SCHED_DENSE = 2 } ttc_sched;
+
+/* TT tensor descriptor. */
+typedef struct {
+  int32_t order;          /* N >= 1                                         */
+  const int32_t* modes;   /* host [N]: I[k] >= 1                            */
+  const int32_t* ranks;   /* host [N+1]: ranks[0] = ranks[N] = 1            */
+  ttc_dtype dtype;        /* element type of every core                     */
+  void* const* cores;     /* host [N] of device pointers                    */
+} ttc_tt;
+
+/* TT-matrix (MPO) descriptor. */
+typedef struct {
+  int32_t order;
+  const int32_t* rows;    /* host [N]: I[k], the output (row) modes          */
+  const int32_t* cols;    /* host [N]: J[k], the input (column) modes        */
+  const int32_t* ranks;   /* host [N+1]                                     */
+  ttc_dtype dtype;
+  void* const* cores;     /* host [N] of device pointers, (R, I, J, R')     */
+} ttc_ttm;
+
+/* ------------------------------------------------------------------------
+ * Inner product <X, Y> = sum over all indices of X[i] Y[i]: the contraction
+ * of two TTs along every mode (Fig. 1(b), all-mode contraction), computed by
+ * interface sweeps.  Left to right, W_0 = [1] and
+ *   W_k = sum_i G_x^(k)[:, i, :]^T W_{k-1} G_y^(k)[:, i, :]   (R_k x P_k);
+ * the first step is the paper's K = A_x^T A_y (Section III, Example 1 and
+ * Algorithm 2, step 4).  Right to left, V_N = [1] and
+ *   V_{k-1} = sum_i G_x^(k)[:, i, :] V_k G_y^(k)[:, i, :]^T.
+ * The two sweeps meet at a middle bond c: z = sum W_c .* V_c, accumulated in
+ * FP64.  X and Y need equal order and mode sizes; their ranks may differ.
+ * x, y:   descriptors, same dtype.
+ * prec:   AUTO, or the precision AUTO would pick.
+ * d_out:  device pointer to one double (written).
+ * d_ws:   device scratch of at least the size tt_contract_inner_query
+ *         returns (may be NULL when that size is 0).
+ * ------------------------------------------------------------------------ */
+ttc_status tt_contract_inner_query(const ttc_tt* x, const ttc_tt* y, ttc_prec prec,
+                                   size_t* ws_bytes);
+ttc_status tt_contract_inner(const ttc_tt* x, const ttc_tt* y, ttc_prec prec, double* d_out,
+                             void* d_ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Contraction of X and Y over a set of shared positions, each pair summed
+ * as in eq. (8) (Def. 6).  The GPU path accepts a prefix {0..k-1}, a suffix
+ * {k..N-1} or all positions, at equal positions and sizes in X and Y.
+ * Prefix: K = W_k (R_k x P_k).  Suffix: K = V_k.  All: the scalar <X, Y>.
+ *
+ * modes / n_modes: host array of 0-based positions (any order, no repeats).
+ * form: JUNCTION writes K (row-major, FP64 for FP64 inputs, FP32 otherwise)
+ *       to out_junction; NATURAL_TT writes the cores of the natural-order TT
+ *       into out_tt (shapes from the query; FP64 or FP32); DENSE writes the
+ *       row-major dense tensor over (X free modes, Y free modes) to out_dense.
+ *       When every position is contracted the scalar is written as one
+ *       double to out_scalar whatever the form.
+ * Natural-order construction (Q = columns of K, q its index):
+ *   prefix: C_k[0, i, s*Q+q] = sum_r K[r,q] G_x^(k)[r,i,s];
+ *           C_m[(s,q), i, (s',q')] = G_x^(m)[s,i,s'] delta(q,q') for m > k;
+ *           then Y's cores k..N-1 unchanged.
+ *   suffix: X's cores 0..k-2 unchanged; C_{k-1}[s,i,q] = sum_r G_x^(k-1)[s,i,r] K[r,q];
+ *           Y's cores m < k-1: D_m[(p,q), j, (p',q')] = G_y^(m)[p,j,p'] delta(q,q');
+ *           D_{k-1}[(p,q), j, 0] = G_y^(k-1)[p, j, q].
+ * The query fills out_order, out_modes[<= 2N], out_ranks[<= 2N+1] (natural
+ * TT or dense shape; junction: order 2 and K's shape in out_ranks[0..1]),
+ * the output element count and the scratch size.
+ * ------------------------------------------------------------------------ */
+ttc_status tt_contract_modes_query(const ttc_tt* x, const ttc_tt* y, const int32_t* modes,
+                                   int32_t n_modes, ttc_form form, int32_t* out_order,
+                                   int32_t* out_modes, int32_t* out_ranks, int64_t* out_elems,
+                                   size_t* ws_bytes);
+ttc_status tt_contract_modes(const ttc_tt* x, const ttc_tt* y, const int32_t* modes,
+                             int32_t n_modes, ttc_form form, void* out_junction,
+                             const ttc_tt* out_tt, void* out_dense, double* out_scalar,
+                             void* d_ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Mode-n products Y = X x_{n} A_n for every listed mode (Def. 5).  On a TT
+ * only core n changes: G'[r, j, s] = sum_i A[j, i] G[r, i, s]; ranks are
+ * unchanged and products on different modes commute.
+ * count / modes: host list of distinct 0-based modes.
+ * d_A[c]: device pointer to a row-major J[c] x I[modes[c]] matrix, x's dtype.
+ * y: output descriptor (same order and ranks as x, mode modes[c] of size
+ *    J[c]); only y->cores[modes[c]] are written, the other entries of
+ *    y->cores are not touched (they may alias x's cores).
+ * ------------------------------------------------------------------------ */
+ttc_status tt_mode_n_product(const ttc_tt* x, int32_t count, const int32_t* modes,
+                             const void* const* d_A, const int32_t* J, const ttc_tt* y,
+                             void* stream);
+
+/* ------------------------------------------------------------------------
+ * TT-matrix times TT-vector on cores:
+ *   C^(k)[(a,r), i, (a',r')] = sum_j W^(k)[a, i, j, a'] V^(k)[r, j, r'],
+ * merged bond index a*R_v + r, output ranks the products of the input ranks.
+ * m->cols must equal v->modes.  Output cores are FP32 for BF16/FP32 inputs
+ * (FP32 accumulation; prec BF16 or AUTO uses the BF16 matrix cores for BF16
+ * inputs) and FP64 for FP64 inputs.  The query returns the output ranks
+ * (host array of order+1) and element count; `out` must have those shapes.
+ * ------------------------------------------------------------------------ */
+ttc_status ttm_apply_query(const ttc_ttm* m, const ttc_tt* v, int32_t* out_ranks,
+                           int64_t* out_elems);
+ttc_status ttm_apply(const ttc_ttm* m, const ttc_tt* v, ttc_prec prec, const ttc_tt* out,
+                     void* stream);
+
+/* ------------------------------------------------------------------------
+ * TT-matrix times a dense batch (a TT layer): Y[b, :] = W X[b, :] for each
+ * of `batch` rows; X is batch x prod(J) and Y is batch x prod(I), both
+ * row-major FP32 with little-endian row vectors (Def. 3); the rows of the
+ * batch are the stacking mode of Def. 4.  Cores are FP32.  prec AUTO/F32:
+ * FP32 matrix cores; BF16: operands rounded to BF16, FP32 accumulation.
+ * sched: see ttc_sched.  Backward: given dY, writes dX = dY W (skipped when
+ * d_dx is NULL) and dW^(k) for every core into d_dcores[k] (FP32, the core's
+ * shape; skipped when d_dcores is NULL).
+ * ------------------------------------------------------------------------ */
+ttc_status ttm_apply_dense_query(const ttc_ttm* m, int64_t batch, ttc_prec prec, ttc_sched sched,
+                                 int32_t backward, size_t* ws_bytes);
+ttc_status ttm_apply_dense(const ttc_ttm* m, const void* d_x, int64_t batch, void* d_y,
+                           ttc_prec prec, ttc_sched sched, void* d_ws, size_t ws_bytes,
+                           void* stream);
+ttc_status ttm_apply_dense_bwd(const ttc_ttm* m, const void* d_x, const void* d_dy, int64_t batch,
+                               void* d_dx, void* const* d_dcores, ttc_prec prec, ttc_sched sched,
+                               void* d_ws, size_t ws_bytes, void* stream);
+
+/* Mean squared error L = mean((y - t)^2) over n FP32 entries, accumulated
+ * in FP64 into d_loss (one double), and dL/dy = 2 (y - t) / n into d_dy
+ * (FP32, skipped when NULL).  Scratch: ttc_mse_loss_query bytes. */
+ttc_status ttc_mse_loss_query(int64_t n, size_t* ws_bytes);
+ttc_status ttc_mse_loss(const float* d_y, const float* d_t, int64_t n, double* d_loss, float* d_dy,
+                        void* d_ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Gradient of z = <X, Y> with respect to every core, scaled by the upstream
+ * gradient *d_gz (one device double):
+ *   dz/dG_x^(k)[:, i, :] = W_k G_y^(k)[:, i, :] V_{k+1}^T,
+ *   dz/dG_y^(k)[:, i, :] = W_k^T G_x^(k)[:, i, :] V_{k+1},
+ * with W_k the left interface of core k and V_{k+1} the right one.  Only every
+ * ckpt_stride-th interface is kept; the rest are recomputed (ckpt_stride <= 0
+ * picks about sqrt(N)).  d_dx[k], d_dy[k]: device buffers shaped like the
+ * cores, same dtype class (FP64 for FP64, FP32 otherwise); either list may
+ * be NULL to skip that side.
+ * ------------------------------------------------------------------------ */
+ttc_status tt_contract_inner_bwd_query(const ttc_tt* x, const ttc_tt* y, int32_t ckpt_stride,
+                                       size_t* ws_bytes);
+ttc_status tt_contract_inner_bwd(const ttc_tt* x, const ttc_tt* y, const double* d_gz,
+                                 void* const* d_dx, void* const* d_dy, int32_t ckpt_stride,
+                                 void* d_ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Batched execution: many independent pairs of uneven order, mode sizes and
+ * ranks in one persistent launch, replayed from a HIP graph.  For each pair
+ * p the right-to-left sweep gives both results:
+ *   TTC_OP_INNER:   d_inner[p] = <X_p, Y_p> (FP64);
+ *   TTC_OP_SUFFIX2: the junction K = V_{N-2} of the contraction over the last
+ *                   two positions, row-major FP32 at d_junction +
+ *                   junction_offset[p] elements (offsets from
+ *                   tt_batch_plan_info).
+ * Pairs need order >= 2 (SUFFIX2: >= 3) and order <= 64; X and Y of a pair
+ * share dtype (FP32 or BF16) and mode sizes.  The plan copies every
+ * descriptor (shapes and core pointers) when it is created; the core buffers
+ * must stay alive and unchanged in place until the plan is destroyed.
+ * tt_batch_plan_create synchronises the device once (descriptor upload and
+ * tile selection).
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  ttc_tt x;
+  ttc_tt y;
+} ttc_pair;
+
+typedef struct ttc_plan ttc_plan;
+
+#define TTC_OP_INNER 1u
+#define TTC_OP_SUFFIX2 2u
+
+ttc_status tt_batch_plan_create(const ttc_pair* pairs, int32_t n, uint32_t ops, ttc_prec prec,
+                                ttc_plan** plan);
+/* junction_offsets: host array of n+1 int64 (may be NULL); flops / bytes:
+ * algorithmic FLOPs and bytes of one run (may be NULL). */
+ttc_status tt_batch_plan_info(const ttc_plan* plan, int64_t* junction_offsets, double* flops,
+                              double* bytes);
+ttc_status tt_batch_run(ttc_plan* plan, double* d_inner, float* d_junction, void* stream);
+/* The same pairs as one single-pair launch sequence each (the plain loop
+ * that the batched launch replaces); same outputs. */
+ttc_status tt_batch_run_plain(ttc_plan* plan, double* d_inner, float* d_junction, void* stream);
+void tt_batch_plan_destroy(ttc_plan* plan);
+
+/* ------------------------------------------------------------------------ */
+const char* ttc_last_error(void); /* thread-local; "" when none            */
+const char* ttc_version(void);
+int32_t ttc_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TTC_H */

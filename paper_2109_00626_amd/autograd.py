@@ -1,0 +1,58 @@
+"""torch.autograd wrappers over the hand-written adjoints in libttc.so.
+
+TTInner: z = <X, Y> with gradients for every core of X and Y (adjoint
+sweeps that keep every c-th interface and recompute the rest).
+TTLinear: y = W x for a TT-matrix W, gradients for the input batch and every
+core.  Both save only their inputs."""
+from __future__ import annotations
+
+import torch
+
+from . import api
+
+
+class TTInner(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, n_x: int, ckpt_stride: int, *cores):
+        x, y = list(cores[:n_x]), list(cores[n_x:])
+        ctx.n_x = n_x
+        ctx.ckpt_stride = ckpt_stride
+        ctx.save_for_backward(*cores)
+        return api.tt_contract_inner(x, y)
+
+    @staticmethod
+    def backward(ctx, gz):
+        cores = ctx.saved_tensors
+        x, y = list(cores[:ctx.n_x]), list(cores[ctx.n_x:])
+        nx = any(ctx.needs_input_grad[2:2 + ctx.n_x])
+        ny = any(ctx.needs_input_grad[2 + ctx.n_x:])
+        gx, gy = api.tt_contract_inner_bwd(x, y, gz.detach(), ckpt_stride=ctx.ckpt_stride, need_x=nx, need_y=ny)
+        gx = [g.to(c.dtype) for g, c in zip(gx, x)] if gx is not None else [None] * len(x)
+        gy = [g.to(c.dtype) for g, c in zip(gy, y)] if gy is not None else [None] * len(y)
+        return (None, None, *gx, *gy)
+
+
+def tt_inner(x, y, ckpt_stride: int = 0):
+    return TTInner.apply(len(x), ckpt_stride, *x, *y)
+
+
+class TTLinear(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, x, prec: str, sched: str, *cores):
+        ctx.prec, ctx.sched = prec, sched
+        ctx.save_for_backward(x, *cores)
+        return api.ttm_apply_dense(list(cores), x, prec=prec, sched=sched)
+
+    @staticmethod
+    def backward(ctx, dy):
+        x, *cores = ctx.saved_tensors
+        dx, dcores = api.ttm_apply_dense_bwd(list(cores), x, dy.contiguous(), prec=ctx.prec, sched=ctx.sched,
+                                             need_dx=ctx.needs_input_grad[0],
+                                             need_dw=any(ctx.needs_input_grad[3:]))
+        if dcores is None:
+            dcores = [None] * len(cores)
+        return (dx, None, None, *dcores)
+
+
+def tt_linear(x, cores, prec: str = "auto", sched: str = "auto"):
+    return TTLinear.apply(x, prec, sched, *cores)

@@ -1,0 +1,119 @@
+// Internal interface between the host runtime (validation, planning,
+// dispatch) and the kernel launchers.  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/ttc.h"
+
+namespace ttc {
+
+// TT descriptor passed by value to kernels (device core pointers).
+struct TTDev {
+  int order;
+  int modes[TTC_MAX_ORDER];
+  int ranks[TTC_MAX_ORDER + 1];
+  const void* cores[TTC_MAX_ORDER];
+};
+
+// ---------------------------------------------------------------- sweeps
+// Block b runs direction dir[b] (0: left to right, 1: right to left,
+// -1: idle) up to bond stop[b] and stores the final interface (row-major
+// R x P, compute type) at out[b].
+struct SweepArgs {
+  TTDev x, y;
+  int dir[2];
+  int stop[2];
+  void* out[2];
+  int max_rp;      // interface buffer capacity (elements)
+  int tcap;        // capacity of the per-mode intermediate (elements)
+  void* t_global;  // intermediate in global memory (null: in LDS)
+  long t_stride;   // elements per block in t_global
+};
+
+// Left/right checkpoints for the inner-product gradient (phase A) and the
+// per-segment gradient pass (phase B).
+struct GradArgs {
+  TTDev x, y;
+  int stride;       // checkpoint stride c
+  int nseg;         // ceil(N / c)
+  void* ckW;        // nseg x max_rp: W_{s c}
+  void* ckV;        // nseg x max_rp: V_{min((s+1)c, N)}
+  void* segV;       // nseg x c x max_rp: V_{k+1} for k in segment s
+  void* dx[TTC_MAX_ORDER];
+  void* dy[TTC_MAX_ORDER];
+  const double* gz;
+  int max_rp;
+  int tcap;
+  void* t_global;
+  long t_stride;
+};
+
+// Natural-order lift of a junction matrix K (see tt_contract_modes).
+enum LiftOp { LIFT_COPY = 0, LIFT_ABSORB_L = 1, LIFT_ABSORB_R = 2, LIFT_DELTA = 3, LIFT_DELTA_LAST = 4 };
+struct LiftCore {
+  int op;
+  int r0, n, r1;     // source core shape
+  int d0, d1;        // destination bond sizes (n is shared)
+  int line_begin;    // first line (d0 x n lines of d1 elements) of this core
+  const void* src;
+  void* dst;
+};
+#define TTC_MAX_LIFT (2 * TTC_MAX_ORDER)
+struct LiftArgs {
+  int ncores;
+  int Q;             // columns of K
+  int kr;            // rows of K
+  const void* K;     // compute type
+  LiftCore c[TTC_MAX_LIFT];
+};
+
+struct DenseArgs {
+  TTDev t;           // compute-type cores
+  long numel;
+  void* out;
+};
+
+// Mode-n products: one entry per listed mode.
+struct ModeNEntry {
+  int r0, I, r1, J;
+  long first;        // first output element of this entry (global numbering)
+  const void* src;
+  const void* A;
+  void* dst;
+};
+struct ModeNArgs {
+  int count;
+  long total;
+  ModeNEntry e[TTC_MAX_ORDER];
+};
+
+// TT-matrix x TT-vector, one entry per core.
+struct MpoCore {
+  int a0, I, J, a1;  // MPO core shape
+  int r0, r1;        // TT-vector core bonds
+  int blk_begin;     // first workgroup of this core
+  const void* w;
+  const void* v;
+  void* out;
+};
+struct MpoArgs {
+  int ncores;
+  int nblk;
+  MpoCore c[TTC_MAX_ORDER];
+};
+
+// launchers (return the launch status)
+hipError_t launch_sweep(ttc_dtype dt, const SweepArgs& a, int nblocks, size_t lds, hipStream_t s);
+hipError_t launch_meet(ttc_dtype dt, const void* W, const void* V, int n, double* out, hipStream_t s);
+hipError_t launch_grad_ckpt(ttc_dtype dt, const GradArgs& a, size_t lds, hipStream_t s);
+hipError_t launch_grad_seg(ttc_dtype dt, const GradArgs& a, size_t lds, hipStream_t s);
+hipError_t launch_lift(ttc_dtype dt, const LiftArgs& a, int total_lines, hipStream_t s);
+hipError_t launch_dense(bool f64, const DenseArgs& a, hipStream_t s);
+hipError_t launch_mode_n(ttc_dtype dt, const ModeNArgs& a, hipStream_t s);
+hipError_t launch_mpo(ttc_dtype dt, bool bf16_mfma, const MpoArgs& a, hipStream_t s);
+hipError_t sweep_set_lds_limits();
+
+int lds_limit_bytes();
+
+}  // namespace ttc

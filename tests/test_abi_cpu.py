@@ -1,0 +1,173 @@
+"""CPU-only checks of the C ABI: the library loads, exports every declared
+entry point, and validates descriptors on the host (before any GPU call),
+returning the documented status and writing nothing.  Shape bookkeeping of
+the queries is compared with the oracle's constructions."""
+import ctypes
+import os
+import re
+from ctypes import byref, c_int32, c_int64, c_size_t, c_void_p
+
+import numpy as np
+import pytest
+
+from oracle import tt_oracle as O
+from ttgen import configs as C
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ttc.h")
+LIB = os.path.join(ROOT, "paper_2109_00626_amd", "libttc.so")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_2109_00626_amd import build
+        build.build(verbose=False)
+    from paper_2109_00626_amd import _abi
+    return _abi.load(LIB)
+
+
+@pytest.fixture(scope="module")
+def abi():
+    from paper_2109_00626_amd import _abi
+    return _abi
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^(?:ttc_status|const char\*|int32_t|void)\s+(\w+)\s*\(", text, flags=re.M)))
+
+
+def test_exports_every_declared_symbol(lib, abi):
+    names = declared_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(abi.EXPORTED)
+    assert lib.ttc_abi_version() == 1
+    assert b"gfx950" in lib.ttc_version()
+
+
+FAKE = 0x7F0000001000  # never dereferenced: validation fails or only queries run
+
+
+class Desc:
+    def __init__(self, abi, modes, ranks, dtype=1):
+        self.m = (c_int32 * len(modes))(*modes)
+        self.r = (c_int32 * len(ranks))(*ranks)
+        self.c = (c_void_p * len(modes))(*[FAKE + 4096 * k for k in range(len(modes))])
+        self.s = abi.TT(len(modes), self.m, self.r, dtype, self.c)
+
+
+def status_name(abi, s):
+    return abi.STATUS_NAMES[s]
+
+
+def test_inner_validation(lib, abi):
+    need = c_size_t(0)
+    x = Desc(abi, [3, 4], [1, 2, 1])
+    y = Desc(abi, [3, 4], [1, 5, 1])
+    assert lib.tt_contract_inner_query(byref(x.s), byref(y.s), 0, byref(need)) == 0
+    assert need.value > 0
+    bad = Desc(abi, [3, 4], [2, 2, 1])
+    assert status_name(abi, lib.tt_contract_inner_query(byref(bad.s), byref(y.s), 0, byref(need))) == "TTC_ERR_RANK"
+    assert b"boundary" in lib.ttc_last_error()
+    other = Desc(abi, [3, 5], [1, 2, 1])
+    assert status_name(abi, lib.tt_contract_inner_query(byref(x.s), byref(other.s), 0, byref(need))) == "TTC_ERR_SHAPE"
+    d64 = Desc(abi, [3, 4], [1, 2, 1], dtype=0)
+    assert status_name(abi, lib.tt_contract_inner_query(byref(x.s), byref(d64.s), 0, byref(need))) == "TTC_ERR_DTYPE"
+    assert status_name(abi, lib.tt_contract_inner_query(None, byref(y.s), 0, byref(need))) == "TTC_ERR_NULL"
+    assert status_name(abi, lib.tt_contract_inner_query(byref(x.s), byref(y.s), 1, byref(need))) == "TTC_ERR_UNSUPPORTED"
+    # workspace too small and NULL output: rejected before any launch
+    out = c_void_p(FAKE)
+    assert status_name(abi, lib.tt_contract_inner(byref(x.s), byref(y.s), 0, out, c_void_p(FAKE), 1, None)) == \
+        "TTC_ERR_WORKSPACE"
+    assert status_name(abi, lib.tt_contract_inner(byref(x.s), byref(y.s), 0, None, c_void_p(FAKE), 1 << 30, None)) == \
+        "TTC_ERR_NULL"
+    zero = Desc(abi, [3, 0], [1, 2, 1])
+    assert status_name(abi, lib.tt_contract_inner_query(byref(zero.s), byref(y.s), 0, byref(need))) == "TTC_ERR_SHAPE"
+
+
+def _modes_query(lib, abi, x, y, modes, form):
+    m = (c_int32 * len(modes))(*modes)
+    order = c_int32(0)
+    om = (c_int32 * 64)()
+    orr = (c_int32 * 65)()
+    el = c_int64(0)
+    ws = c_size_t(0)
+    st = lib.tt_contract_modes_query(byref(x.s), byref(y.s), m, len(modes), form, byref(order), om, orr, byref(el),
+                                     byref(ws))
+    return st, order.value, list(om[:order.value]), list(orr[:order.value + 1]), el.value
+
+
+@pytest.mark.parametrize("which", ["pair10", "inner4"])
+def test_modes_query_matches_oracle_shapes(lib, abi, which):
+    if which == "pair10":
+        sx, sy = C.pair10_shapes()
+        modes = [0, 1, 2, 3, 4]
+    else:
+        sx, sy = C.inner4_shapes()
+        modes = [2, 3]
+    x = Desc(abi, sx.modes, sx.ranks)
+    y = Desc(abi, sy.modes, sy.ranks)
+    st, order, om, orr, el = _modes_query(lib, abi, x, y, modes, abi.FORM["natural"])
+    assert st == 0
+    xs = [np.zeros(sx.core_shape(k)) for k in range(sx.order)]
+    ys = [np.zeros(sy.core_shape(k)) for k in range(sy.order)]
+    want = O.contract_natural(xs, ys, modes)
+    assert om == O.tt_modes(want)
+    assert orr == O.tt_ranks(want)
+    assert el == sum(G.size for G in want)
+    st, order, om, orr, el = _modes_query(lib, abi, x, y, modes, abi.FORM["dense"])
+    assert st == 0 and el == int(np.prod(O.tt_modes(want)))
+
+
+def test_modes_query_errors(lib, abi):
+    x = Desc(abi, [3, 4, 5], [1, 2, 2, 1])
+    y = Desc(abi, [3, 4, 5], [1, 3, 3, 1])
+    assert status_name(abi, _modes_query(lib, abi, x, y, [1], 0)[0]) == "TTC_ERR_UNSUPPORTED"
+    assert status_name(abi, _modes_query(lib, abi, x, y, [0, 0], 0)[0]) == "TTC_ERR_MODE"
+    assert status_name(abi, _modes_query(lib, abi, x, y, [3], 0)[0]) == "TTC_ERR_MODE"
+    st, order, _, orr, el = _modes_query(lib, abi, x, y, [2, 1], 0)
+    assert st == 0 and order == 2 and orr[:2] == [2, 3] and el == 6   # suffix K = V_1 (R_1 x P_1)
+    st, order, _, _, el = _modes_query(lib, abi, x, y, [0, 1, 2], 1)
+    assert st == 0 and order == 0 and el == 1
+
+
+def test_mpo_query(lib, abi):
+    sw, sv = C.mpo8_shapes()
+    rows = (c_int32 * 8)(*sw.modes)
+    cols = (c_int32 * 8)(*sw.cols)
+    rk = (c_int32 * 9)(*sw.ranks)
+    cores = (c_void_p * 8)(*[FAKE] * 8)
+    m = abi.TTM(8, rows, cols, rk, 2, cores)
+    v = Desc(abi, sv.modes, sv.ranks, dtype=2)
+    orr = (c_int32 * 9)()
+    el = c_int64(0)
+    assert lib.ttm_apply_query(byref(m), byref(v.s), orr, byref(el)) == 0
+    assert list(orr) == [1] + [1024] * 7 + [1]
+    assert el.value == 2 * 32 * 1024 + 6 * 1024 * 32 * 1024
+    v2 = Desc(abi, [32] * 7 + [16], sv.ranks, dtype=2)
+    assert status_name(abi, lib.ttm_apply_query(byref(m), byref(v2.s), orr, byref(el))) == "TTC_ERR_SHAPE"
+
+
+def test_mode_n_validation(lib, abi):
+    x = Desc(abi, [3, 4], [1, 2, 1])
+    y = Desc(abi, [3, 6], [1, 2, 1])
+    A = (c_void_p * 1)(FAKE)
+    J = (c_int32 * 1)(5)
+    m = (c_int32 * 1)(1)
+    assert status_name(abi, lib.tt_mode_n_product(byref(x.s), 1, m, A, J, byref(y.s), None)) == "TTC_ERR_SHAPE"
+    m2 = (c_int32 * 1)(2)
+    assert status_name(abi, lib.tt_mode_n_product(byref(x.s), 1, m2, A, J, byref(y.s), None)) == "TTC_ERR_MODE"
+
+
+def test_grad_query(lib, abi):
+    sx, sy = C.pair10_shapes()
+    x = Desc(abi, sx.modes, sx.ranks)
+    y = Desc(abi, sy.modes, sy.ranks)
+    a, b = c_size_t(0), c_size_t(0)
+    assert lib.tt_contract_inner_bwd_query(byref(x.s), byref(y.s), 1, byref(a)) == 0
+    assert lib.tt_contract_inner_bwd_query(byref(x.s), byref(y.s), 4, byref(b)) == 0
+    assert a.value > 0 and b.value > 0

@@ -1,0 +1,279 @@
+"""GPU parity of the single-pair operations against the FP64 oracle, called
+through the C ABI: inner products, shared-block contractions (junction,
+natural and dense forms), mode-n products, MPO x TT, and the inner-product
+gradient.  Tolerances: FP64 1e-12, FP32 1e-5, BF16 inputs 2e-2 (relative,
+measured as documented in helpers)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import tt_oracle as O
+from ttgen import configs as C
+
+from helpers import TOL, max_core_rel, random_pair, rel_fro, scalar_err, to_gpu, to_np, tt_norm
+
+pytestmark = pytest.mark.gpu
+
+
+def _inner_case(ttc, x, y, dtype):
+    xg, xs = to_gpu(x, dtype)
+    yg, ys = to_gpu(y, dtype)
+    z = float(ttc.tt_contract_inner(xg, yg).item())
+    # arithmetic error: oracle on the values the GPU holds
+    zr = O.inner_lr(xs, ys)
+    e = scalar_err(z, zr, tt_norm(xs), tt_norm(ys))
+    # total error: oracle on the unrounded FP64 inputs
+    et = scalar_err(z, O.inner_lr(x, y), tt_norm(x), tt_norm(y))
+    return e, et
+
+
+# ------------------------------------------------------------------ inner
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+def test_inner_inner4(ttc, dtype):
+    sx, sy = C.inner4_shapes()
+    x = C.gen_tt_np(C.SEED_INNER4, 1, sx)
+    y = C.gen_tt_np(C.SEED_INNER4, 2, sy)
+    e, et = _inner_case(ttc, x, y, dtype)
+    print(f"inner4 {dtype}: arithmetic {e:.3e} total {et:.3e}")
+    assert (et if dtype == "bf16" else e) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_inner_pair10(ttc, dtype):
+    sx, sy = C.pair10_shapes()
+    x = C.gen_tt_np(C.SEED_PAIR10, 1, sx)
+    y = C.gen_tt_np(C.SEED_PAIR10, 2, sy)
+    e, et = _inner_case(ttc, x, y, dtype)
+    print(f"pair10 {dtype}: arithmetic {e:.3e} total {et:.3e}")
+    assert (et if dtype == "bf16" else e) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("case", [
+    ([3, 5, 2, 7, 4], [1, 3, 17, 5, 2, 1], [1, 9, 2, 33, 6, 1]),          # ragged ranks
+    ([64, 4], [1, 70, 1], [1, 37, 1]),                                      # several tiles, ragged tail
+    ([5], [1, 1], [1, 1]),                                                  # order 1
+    ([16, 32, 8], [1, 128, 100, 1], [1, 90, 128, 1]),                       # large ranks
+    ([2, 3, 2, 3, 2, 3, 2], [1, 2, 3, 4, 5, 4, 3, 1], [1, 1, 2, 1, 2, 1, 2, 1]),
+])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_inner_ragged(ttc, case, dtype):
+    modes, rx, ry = case
+    x, y = random_pair(77, modes, rx, ry)
+    e, _ = _inner_case(ttc, x, y, dtype)
+    assert e <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+def test_inner_integer_cores_bit_exact(ttc, dtype):
+    s = C.TTShape([4, 8, 3, 5, 6], [1, 5, 7, 3, 4, 1])
+    x = C.gen_int_tt_np(31, 1, s)
+    y = C.gen_int_tt_np(31, 2, s)
+    want = O.inner_lr(x, y)  # exact: integer partial sums well below 2^24
+    xg, _ = to_gpu(x, dtype)
+    yg, _ = to_gpu(y, dtype)
+    z = float(ttc.tt_contract_inner(xg, yg).item())
+    assert z == want
+
+
+def test_inner_deterministic(ttc):
+    sx, sy = C.pair10_shapes()
+    xg, _ = to_gpu(C.gen_tt_np(C.SEED_PAIR10, 1, sx), "f32")
+    yg, _ = to_gpu(C.gen_tt_np(C.SEED_PAIR10, 2, sy), "f32")
+    a = ttc.tt_contract_inner(xg, yg).item()
+    b = ttc.tt_contract_inner(xg, yg).item()
+    assert a == b
+
+
+# ------------------------------------------------------------------ modes
+def test_modes_inner4_all_forms(ttc):
+    sx, sy = C.inner4_shapes()
+    x = C.gen_tt_np(C.SEED_INNER4, 1, sx)
+    y = C.gen_tt_np(C.SEED_INNER4, 2, sy)
+    xg, _ = to_gpu(x, "f64")
+    yg, _ = to_gpu(y, "f64")
+    modes = [2, 3]  # the paper's modes 3-4
+    K = to_np(ttc.tt_contract_modes(xg, yg, modes, "junction"))
+    assert rel_fro(K, O.contract_junction(x, y, modes)[2]) <= TOL["f64"]
+    nat = [to_np(t) for t in ttc.tt_contract_modes(xg, yg, modes, "natural")]
+    want = O.contract_natural(x, y, modes)
+    assert [G.shape for G in nat] == [G.shape for G in want]
+    assert max_core_rel(nat, want) <= TOL["f64"]
+    Z = to_np(ttc.tt_contract_modes(xg, yg, modes, "dense"))
+    assert Z.shape == (8, 8, 8, 8)
+    assert rel_fro(Z, O.contract_dense(x, y, modes)) <= TOL["f64"]
+    z = ttc.tt_contract_modes(xg, yg, [3, 1, 0, 2], "natural").item()
+    assert scalar_err(z, O.inner_lr(x, y), tt_norm(x), tt_norm(y)) <= TOL["f64"]
+
+
+@pytest.mark.parametrize("modes", [[0], [0, 1], [0, 1, 2], [3], [1, 2, 3], [2, 3]])
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+def test_modes_ragged_prefix_suffix(ttc, modes, dtype):
+    x, y = random_pair(91, [3, 5, 2, 4], [1, 3, 6, 2, 1], [1, 2, 5, 7, 1])
+    xg, xs = to_gpu(x, dtype)
+    yg, ys = to_gpu(y, dtype)
+    ref = (x, y) if dtype == "bf16" else (xs, ys)
+    tol = TOL[dtype]
+    K = to_np(ttc.tt_contract_modes(xg, yg, modes, "junction"))
+    assert rel_fro(K, O.contract_junction(*ref, modes)[2]) <= tol
+    nat = [to_np(t) for t in ttc.tt_contract_modes(xg, yg, modes, "natural")]
+    assert max_core_rel(nat, O.contract_natural(*ref, modes)) <= tol
+    Z = to_np(ttc.tt_contract_modes(xg, yg, modes, "dense"))
+    assert rel_fro(Z, O.contract_dense(*ref, modes)) <= tol
+
+
+def test_modes_pair10_prefix5(ttc):
+    """Modes 1-5 of the order-10 pair: junction, then the natural TT with
+    ranks 32*32 at full size, checked core by core."""
+    sx, sy = C.pair10_shapes()
+    x = C.gen_tt_np(C.SEED_PAIR10, 1, sx)
+    y = C.gen_tt_np(C.SEED_PAIR10, 2, sy)
+    xg, xs = to_gpu(x, "f32")
+    yg, ys = to_gpu(y, "f32")
+    modes = [0, 1, 2, 3, 4]
+    K = to_np(ttc.tt_contract_modes(xg, yg, modes, "junction"))
+    Kr = O.contract_junction(xs, ys, modes)[2]
+    assert rel_fro(K, Kr) <= TOL["f32"]
+    nat = ttc.tt_contract_modes(xg, yg, modes, "natural")
+    want = O.contract_natural(xs, ys, modes)
+    assert [tuple(t.shape) for t in nat] == [G.shape for G in want]
+    assert [int(t.shape[0]) for t in nat] + [1] == [1, 1024, 1024, 1024, 1024, 32, 32, 32, 32, 32, 1]
+    for t, w in zip(nat, want):
+        assert rel_fro(to_np(t), w) <= TOL["f32"]
+
+
+def test_modes_unsupported_and_errors(ttc):
+    x, y = random_pair(5, [3, 4, 5], [1, 2, 2, 1], [1, 2, 2, 1])
+    xg, _ = to_gpu(x, "f32")
+    yg, _ = to_gpu(y, "f32")
+    with pytest.raises(ttc.TTCError) as ei:
+        ttc.tt_contract_modes(xg, yg, [1], "junction")  # middle position
+    assert ei.value.name == "TTC_ERR_UNSUPPORTED"
+    with pytest.raises(ttc.TTCError) as ei:
+        ttc.tt_contract_modes(xg, yg, [0, 0], "junction")
+    assert ei.value.name == "TTC_ERR_MODE"
+
+
+# ------------------------------------------------------------------ mode-n
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+def test_mode_n_inner4(ttc, dtype):
+    sx, _ = C.inner4_shapes()
+    x = C.gen_tt_np(C.SEED_INNER4, 1, sx)
+    A = C.gen_matrix_np(C.SEED_INNER4, 3, 8, 8)
+    xg, xs = to_gpu(x, dtype)
+    Ag, As = to_gpu([A], dtype)
+    out = ttc.tt_mode_n_product(xg, [1], Ag)  # the paper's mode 2
+    assert out[0] is xg[0] and out[2] is xg[2]
+    want = O.mode_n_tt(xs, 1, As[0])
+    got = to_np(out[1])
+    if dtype == "bf16":
+        # output rounded to BF16: compare with the FP64 product on the unrounded inputs
+        assert rel_fro(got, O.mode_n_tt(x, 1, A)[1]) <= TOL["bf16"]
+    else:
+        assert rel_fro(got, want[1]) <= TOL[dtype]
+    # dense check against Def. 5 on the reconstructed tensor
+    if dtype == "f64":
+        full = O.tt_full([to_np(t) for t in out])
+        assert rel_fro(full, O.mode_n_product(O.tt_full(x), A, 1)) <= 1e-12
+
+
+def test_mode_n_pair10_every_mode(ttc):
+    sx, _ = C.pair10_shapes()
+    x = C.gen_tt_np(C.SEED_PAIR10, 1, sx)
+    mats = [C.gen_matrix_np(C.SEED_PAIR10, 3 + n, 16, 16) for n in range(10)]
+    xg, xs = to_gpu(x, "f32")
+    Ag, As = to_gpu(mats, "f32")
+    out = ttc.tt_mode_n_product(xg, list(range(10)), Ag)
+    want = xs
+    for n in range(10):
+        want = O.mode_n_tt(want, n, As[n])
+    assert max_core_rel([to_np(t) for t in out], want) <= TOL["f32"]
+
+
+def test_mode_n_identity_and_rectangular(ttc):
+    x, _ = random_pair(12, [5, 7, 3], [1, 4, 6, 1], [1, 1, 1, 1])
+    xg, xs = to_gpu(x, "f32")
+    import torch
+    I7 = torch.eye(7, dtype=torch.float32, device="cuda")
+    out = ttc.tt_mode_n_product(xg, [1], [I7])
+    assert torch.equal(out[1], xg[1])
+    A = C.gen_matrix_np(12, 9, 11, 5)  # J = 11 from I = 5
+    Ag, As = to_gpu([A], "f32")
+    out = ttc.tt_mode_n_product(xg, [0], Ag)
+    assert tuple(out[0].shape) == (1, 11, 4)
+    assert rel_fro(to_np(out[0]), O.mode_n_tt(xs, 0, As[0])[0]) <= TOL["f32"]
+
+
+# ------------------------------------------------------------------ MPO x TT
+def test_mpo_small_dtypes(ttc):
+    sw = C.TTShape([3, 5, 2], [1, 4, 3, 1], [4, 6, 3])
+    sv = C.TTShape([4, 6, 3], [1, 5, 2, 1])
+    w = C.gen_tt_np(41, 1, sw)
+    v = C.gen_tt_np(41, 2, sv)
+    for dtype in ("f64", "f32", "bf16"):
+        wg, ws = to_gpu(w, dtype)
+        vg, vs = to_gpu(v, dtype)
+        out = [to_np(t) for t in ttc.ttm_apply(wg, vg)]
+        want = O.mpo_tt(ws, vs) if dtype != "bf16" else O.mpo_tt(w, v)
+        assert max_core_rel(out, want) <= TOL[dtype], dtype
+    # identity MPO returns V exactly
+    import torch
+    ident = [torch.eye(d, dtype=torch.float32, device="cuda").reshape(1, d, d, 1).contiguous() for d in sv.modes]
+    vg, _ = to_gpu(v, "f32")
+    out = ttc.ttm_apply(ident, vg)
+    assert all(torch.equal(a, b) for a, b in zip(out, vg))
+
+
+def test_mpo8_bf16_full(ttc):
+    """Order-8 MPO (I = J = 32, rank 16) on an order-8 TT (mode 32, rank 64),
+    BF16 inputs, FP32 output with ranks 1024; against the FP64 oracle on the
+    unrounded inputs (two whole cores) and sampled entries of every core."""
+    sw, sv = C.mpo8_shapes()
+    w = C.gen_tt_np(C.SEED_MPO8, 1, sw)
+    v = C.gen_tt_np(C.SEED_MPO8, 2, sv)
+    wg, _ = to_gpu(w, "bf16")
+    vg, _ = to_gpu(v, "bf16")
+    out = ttc.ttm_apply(wg, vg)
+    assert [int(t.shape[0]) for t in out] + [1] == [1] + [1024] * 7 + [1]
+    rs = np.random.RandomState(3)
+    for k in range(8):
+        got = out[k]
+        if k in (0, 4):
+            want = O.mpo_tt([w[k]], [v[k]])[0]
+            assert rel_fro(to_np(got), want) <= TOL["bf16"]
+        # 2000 sampled entries, each from its own definition
+        R0, I, R1 = got.shape
+        idx = [(rs.randint(R0), rs.randint(I), rs.randint(R1)) for _ in range(2000)]
+        g = to_np(got[[i[0] for i in idx], [i[1] for i in idx], [i[2] for i in idx]])
+        Rv0, Rv1 = v[k].shape[0], v[k].shape[2]
+        ref = np.array([w[k][a // Rv0, i, :, b // Rv1] @ v[k][a % Rv0, :, b % Rv1] for a, i, b in idx])
+        scale = np.sqrt(np.mean(ref * ref))
+        assert np.max(np.abs(g - ref)) / scale <= 0.1  # per-entry BF16 rounding, relative to the RMS
+        assert rel_fro(g, ref) <= TOL["bf16"]
+
+
+# ------------------------------------------------------------------ gradient
+@pytest.mark.parametrize("stride", [1, 2, 3, 0])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_inner_grad(ttc, dtype, stride):
+    x, y = random_pair(55, [3, 4, 2, 5, 3, 2, 4], [1, 3, 5, 2, 4, 3, 2, 1], [1, 2, 3, 4, 2, 5, 3, 1])
+    xg, xs = to_gpu(x, dtype)
+    yg, ys = to_gpu(y, dtype)
+    gx, gy = ttc.tt_contract_inner_bwd(xg, yg, 0.75, ckpt_stride=stride)
+    wx, wy = O.inner_grad(xs, ys, 0.75)
+    assert max_core_rel([to_np(t) for t in gx], wx) <= TOL[dtype]
+    assert max_core_rel([to_np(t) for t in gy], wy) <= TOL[dtype]
+
+
+def test_inner_grad_pair10_autograd(ttc):
+    import torch
+    sx, sy = C.pair10_shapes()
+    x = C.gen_tt_np(C.SEED_PAIR10, 1, sx)
+    y = C.gen_tt_np(C.SEED_PAIR10, 2, sy)
+    xg, xs = to_gpu(x, "f32")
+    yg, ys = to_gpu(y, "f32")
+    xv = [t.clone().requires_grad_(True) for t in xg]
+    z = ttc.tt_inner(xv, yg, ckpt_stride=3)
+    z.backward(torch.tensor(2.0, dtype=torch.float64, device="cuda"))
+    wx, _ = O.inner_grad(xs, ys, 2.0)
+    assert max_core_rel([to_np(t.grad) for t in xv], wx) <= TOL["f32"]
