@@ -1,0 +1,397 @@
+"""Benchmark of the TT-contraction hot path on one MI355X.
+
+One step = one pass over every operation of the path, each at its full
+workload size, inputs resident in HBM:
+  pair10 : order-10 FP32 pair (modes 16, ranks 32): inner product, contraction
+           over modes 1-5 written as the natural-order TT (ranks 32*32),
+           mode-n product of all ten modes with 16x16 matrices, and the
+           gradient of the inner product with respect to every core;
+  mpo8   : order-8 MPO (I = J = 32, rank 16) x order-8 TT (mode 32, rank 64),
+           BF16 inputs, FP32 output with ranks 1024;
+  batch  : 4096 uneven FP32 pairs, inner product + junction of the last two
+           positions each, one persistent launch (graph replay);
+  layer4 : order-4 TT-matrix 4096 -> 4096 (modes 8, ranks 32) on a
+           8192 x 4096 FP32 batch: forward, MSE loss, backward (dX and every
+           core gradient).
+value = TT contractions per step / seconds per step.  Beside the step, the
+BF16 batch, the per-pair launch loop and the BF16-MFMA layer are timed once.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"hbm_GBs": 8000.0, "fp32_TFLOPs": 157.3, "bf16_TFLOPs": 2500.0, "fp64_TFLOPs": 78.6}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--parts", default="pair10,mpo8,batch,layer4")
+    return ap.parse_args()
+
+
+# ------------------------------------------------------------- workload setup
+def setup(parts):
+    import torch
+
+    import paper_2109_00626_amd as ttc
+    from ttgen import configs as C
+
+    dev = torch.device("cuda:0")
+    W = {}
+    if "pair10" in parts:
+        sx, sy = C.pair10_shapes()
+        x = C.gen_tt_torch(C.SEED_PAIR10, 1, sx, dev, torch.float32)
+        y = C.gen_tt_torch(C.SEED_PAIR10, 2, sy, dev, torch.float32)
+        A = [C.gen_matrix_torch(C.SEED_PAIR10, 3 + n, 16, 16, dev, torch.float32) for n in range(10)]
+        W["pair10"] = dict(x=x, y=y, A=A, sx=sx, sy=sy)
+    if "mpo8" in parts:
+        sw, sv = C.mpo8_shapes()
+        W["mpo8"] = dict(w=C.gen_tt_torch(C.SEED_MPO8, 1, sw, dev, torch.bfloat16),
+                         v=C.gen_tt_torch(C.SEED_MPO8, 2, sv, dev, torch.bfloat16), sw=sw, sv=sv)
+    if "batch" in parts:
+        shapes = C.batch_pair_shapes(C.SEED_BATCH, 4096)
+        pairs = C.gen_batch_torch(C.SEED_BATCH, shapes, dev, torch.float32)
+        plan = ttc.BatchPlan(pairs)
+        inner, junc = plan.outputs()
+        W["batch"] = dict(shapes=shapes, pairs=pairs, plan=plan, inner=inner, junc=junc)
+    if "layer4" in parts:
+        s = C.layer4_shape()
+        w = C.gen_tt_torch(C.SEED_LAYER, 1, s, dev, torch.float32)
+        X = C.gen_matrix_torch(C.SEED_LAYER, 2, 8192, 4096, dev, torch.float32)
+        T = C.gen_matrix_torch(C.SEED_LAYER, 3, 8192, 4096, dev, torch.float32)
+        W["layer4"] = dict(w=w, X=X, T=T, s=s)
+    torch.cuda.synchronize()
+    return W
+
+
+def run_part(name, W, ttc, prec_layer="f32"):
+    if name == "pair10":
+        d = W["pair10"]
+        ttc.tt_contract_inner(d["x"], d["y"])
+        ttc.tt_contract_modes(d["x"], d["y"], [0, 1, 2, 3, 4], "natural")
+        ttc.tt_mode_n_product(d["x"], list(range(10)), d["A"])
+        ttc.tt_contract_inner_bwd(d["x"], d["y"], 1.0)
+    elif name == "mpo8":
+        d = W["mpo8"]
+        ttc.ttm_apply(d["w"], d["v"])
+    elif name == "batch":
+        d = W["batch"]
+        d["plan"].run(d["inner"], d["junc"])
+    elif name == "layer4":
+        d = W["layer4"]
+        Y = ttc.ttm_apply_dense(d["w"], d["X"], prec=prec_layer)
+        _, dY = ttc.ttc_mse_loss(Y, d["T"])
+        ttc.ttm_apply_dense_bwd(d["w"], d["X"], dY, prec=prec_layer)
+
+
+CONTRACTIONS = {"pair10": 13, "mpo8": 1, "batch": 8192, "layer4": 2}
+
+
+# ------------------------------------------------------------- algorithmic work
+def algorithmic(W):
+    """FLOPs and HBM bytes each part must move at minimum (inputs read once,
+    outputs written once)."""
+    out = {}
+    if "pair10" in W:
+        sx = W["pair10"]["sx"]
+        R, I, N = 32, 16, 10
+        # minimum-order sweep: 2*I*R^3*2 per interior step
+        step = 2 * I * R * R * (R + R)
+        inner = step * (N - 2) + 2 * 2 * I * R * R + 2 * R * R
+        part = step * 4 + 2 * I * R * R
+        nat_elems = 16384 + 3 * 16777216 + 524288 + 4 * 16384 + 512
+        moden = sum(2 * sx.ranks[k] * 16 * 16 * sx.ranks[k + 1] for k in range(N))
+        grad = 2 * inner + 2 * N * 2 * I * R * R * R * 2
+        core_bytes = 4 * 2 * sum(sx.core_numel(k) for k in range(N))
+        out["pair10"] = dict(flops=inner + part + moden + grad,
+                             bytes=core_bytes * 4 + 4 * nat_elems + 4 * sum(sx.core_numel(k) for k in range(N)) * 3)
+    if "mpo8" in W:
+        sw, sv = W["mpo8"]["sw"], W["mpo8"]["sv"]
+        fl = sum(2 * sw.ranks[k] * sw.modes[k] * sw.ranks[k + 1] * sv.ranks[k] * sv.ranks[k + 1] * sw.cols[k]
+                 for k in range(8))
+        outb = 4 * sum(sw.ranks[k] * sv.ranks[k] * sw.modes[k] * sw.ranks[k + 1] * sv.ranks[k + 1] for k in range(8))
+        inb = 2 * (sw.numel() + sv.numel())
+        out["mpo8"] = dict(flops=fl, bytes=outb + inb, out_bytes=outb)
+    if "batch" in W:
+        p = W["batch"]["plan"]
+        out["batch"] = dict(flops=p.flops, bytes=p.bytes)
+    if "layer4" in W:
+        B, D = 8192, 4096
+        gemm = 2.0 * B * D * D
+        chain = 2.0 * (64 * 32 * 64 * 32 + 4096 * 32 * 64 * 32 + 262144 * 32 * 64)
+        proj = 2.0 * (32 * 64 * 262144 + 262144 * 32 * 64 + 32 * 2048 * 4096 + 4096 * 32 * 2048 + 32 * 2048 * 64)
+        fwd = gemm + chain
+        out["layer4"] = dict(flops=fwd + 2 * gemm + chain + proj, fwd_flops=fwd, gemm_flops=gemm,
+                             bytes=4.0 * B * D * 6)
+    return out
+
+
+# ------------------------------------------------------------- CPU baseline
+def cpu_baseline(W, n_contr, budget_s=25.0):
+    """The FP64 oracle as it is, on a bounded sample of each part, each part's
+    time scaled to its full size; returns TT contractions/s of the step."""
+    import numpy as np
+    import torch
+
+    from oracle import tt_oracle as O
+
+    def np_cores(ts):
+        return [t.detach().to(torch.float64).cpu().numpy() for t in ts]
+
+    est, sample = {}, []
+    t_all = time.perf_counter()
+    if "pair10" in W:
+        d = W["pair10"]
+        x, y = np_cores(d["x"]), np_cores(d["y"])
+        A = [a.double().cpu().numpy() for a in d["A"]]
+        t0 = time.perf_counter()
+        O.inner_lr(x, y)
+        O.contract_natural(x, y, [0, 1, 2, 3, 4])
+        z = x
+        for n in range(10):
+            z = O.mode_n_tt(z, n, A[n])
+        O.inner_grad(x, y)
+        est["pair10"] = time.perf_counter() - t0
+        sample.append("pair10 in full")
+    if "mpo8" in W:
+        d = W["mpo8"]
+        w, v = np_cores(d["w"]), np_cores(d["v"])
+        t0 = time.perf_counter()
+        O.mpo_tt([w[3]], [v[3]])
+        t1 = time.perf_counter() - t0
+        fl = [w[k].size * v[k].shape[0] * v[k].shape[2] for k in range(8)]
+        est["mpo8"] = t1 * sum(fl) / fl[3]
+        sample.append("mpo8 core 4 of 8, scaled by FLOPs")
+    if "batch" in W:
+        d = W["batch"]
+        plan = d["plan"]
+        rs = np.random.RandomState(0)
+        idx = rs.choice(len(d["pairs"]), 24, replace=False)
+
+        def pair_flops(sx, sy):
+            return sum(2 * sx.ranks[k] * sx.modes[k] * sx.ranks[k + 1] * (sy.ranks[k] + sy.ranks[k + 1]) * sy.ranks[k + 1]
+                       for k in range(sx.order))
+
+        fl = sum(pair_flops(*d["shapes"][p]) for p in idx)
+        conv = [(np_cores(d["pairs"][p][0]), np_cores(d["pairs"][p][1])) for p in idx]
+        t0 = time.perf_counter()
+        for x, y in conv:
+            O.inner_lr(x, y)
+            O.sweep_rl(x, y, downto=len(x) - 2)
+        t1 = time.perf_counter() - t0
+        full = sum(pair_flops(sx, sy) for sx, sy in d["shapes"])
+        est["batch"] = t1 * full / fl
+        sample.append("batch: 24 random pairs of 4096, scaled by FLOPs")
+    if "layer4" in W:
+        d = W["layer4"]
+        w = np_cores(d["w"])
+        rows = 64
+        X = d["X"][:rows].double().cpu().numpy()
+        T = d["T"][:rows].double().cpu().numpy()
+        t0 = time.perf_counter()
+        Wd = O.mpo_full(w)
+        t_fixed = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        Y = X @ Wd.T
+        L, dY = O.mse_loss(Y, T)
+        dX = dY @ Wd
+        dW = dY.T @ X
+        t_rows = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        O.mpo_core_grads_from_dense(w, dW)
+        t_fixed += time.perf_counter() - t0
+        est["layer4"] = t_fixed + t_rows * (8192 / rows)
+        sample.append("layer4: 64 of 8192 rows (row-proportional work scaled by 128, reconstruction and projection once)")
+    total = sum(est.values())
+    threads = os.cpu_count()
+    try:
+        from threadpoolctl import threadpool_info
+        info = threadpool_info()
+        if info:
+            threads = max(i.get("num_threads", 1) for i in info)
+    except Exception:
+        pass
+    return {
+        "value": n_contr / total if total > 0 else None,
+        "unit": "TT contractions/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": "; ".join(sample) + f"; measured {time.perf_counter() - t_all:.1f} s, estimated full step "
+                                      f"{total:.2f} s",
+        "est_seconds_per_part": {k: round(v, 4) for k, v in est.items()},
+    }
+
+
+# ------------------------------------------------------------- main
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+                                   "(how the path would shard is described in the design notes)"}))
+        sys.exit(2)
+    import torch
+
+    import paper_2109_00626_amd as ttc
+
+    parts = [p for p in args.parts.split(",") if p]
+    W = setup(parts)
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        for p in parts:
+            run_part(p, W, ttc)
+    torch.cuda.synchronize()
+    ev = {p: [] for p in parts}
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        for p in parts:
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            run_part(p, W, ttc)
+            b.record(stream)
+            ev[p].append((a, b))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    part_ms = {p: sum(a.elapsed_time(b) for a, b in ev[p]) / args.steps for p in parts}
+    ms_step = 1e3 * wall / args.steps
+    n_contr = sum(CONTRACTIONS[p] for p in parts)
+    alg = algorithmic(W)
+
+    # the layer forward alone (its GEMM is the largest launch of the step)
+    fwd_ms = None
+    if "layer4" in parts:
+        d = W["layer4"]
+        evs = []
+        for _ in range(max(3, args.steps)):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            ttc.ttm_apply_dense(d["w"], d["X"])
+            b.record(stream)
+            evs.append((a, b))
+        torch.cuda.synchronize()
+        fwd_ms = sorted(a.elapsed_time(b) for a, b in evs)[len(evs) // 2]
+
+    parts_out = {}
+    for p in parts:
+        ms = part_ms[p]
+        o = {"ms": round(ms, 4), "contractions": CONTRACTIONS[p],
+             "TFLOPs": round(alg[p]["flops"] / (ms * 1e-3) / 1e12, 3),
+             "GBs": round(alg[p]["bytes"] / (ms * 1e-3) / 1e9, 1)}
+        parts_out[p] = o
+    dominant = max(parts, key=lambda p: part_ms[p])
+    # roofline of the dominant part's main kernel
+    if dominant == "layer4":
+        gemm_ms = fwd_ms
+        ach = alg["layer4"]["fwd_flops"] / (gemm_ms * 1e-3) / 1e12
+        roof = {"bound": "mfma", "kernel": "gemm_kernel (FP32 16x16x4 MFMA), measured as the whole forward call",
+                "achieved": round(ach, 2), "peak": PEAK["fp32_TFLOPs"], "unit": "TFLOP/s",
+                "frac": round(ach / PEAK["fp32_TFLOPs"], 4), "traffic": None,
+                "per_launch": "2 * 8192 * 4096 * 4096 FLOP (+ 1.1 GFLOP core chain)"}
+    elif dominant == "batch":
+        ms = part_ms["batch"]
+        ach = alg["batch"]["bytes"] / (ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "kernel": "batch_kernel", "achieved": round(ach, 1), "peak": PEAK["hbm_GBs"],
+                "unit": "GB/s", "frac": round(ach / PEAK["hbm_GBs"], 4), "traffic": None}
+    else:
+        ms = part_ms[dominant]
+        ach = alg[dominant]["bytes"] / (ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "kernel": dominant, "achieved": round(ach, 1), "peak": PEAK["hbm_GBs"],
+                "unit": "GB/s", "frac": round(ach / PEAK["hbm_GBs"], 4), "traffic": None}
+
+    beside = {}
+    if "batch" in parts:
+        d = W["batch"]
+        plan = d["plan"]
+
+        def timeit(fn, reps=3):
+            fn()
+            torch.cuda.synchronize()
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            for _ in range(reps):
+                fn()
+            b.record(stream)
+            torch.cuda.synchronize()
+            return a.elapsed_time(b) / reps
+
+        plain_ms = timeit(lambda: plan.run(d["inner"], d["junc"], plain=True), reps=2)
+        beside["batch_fp32"] = {"batched_ms": round(part_ms["batch"], 4), "plain_loop_ms": round(plain_ms, 4),
+                                "contractions_per_s": round(8192 / (part_ms["batch"] * 1e-3), 1),
+                                "GBs": parts_out["batch"]["GBs"], "TFLOPs": parts_out["batch"]["TFLOPs"],
+                                "algorithmic_GB": round(plan.bytes / 1e9, 3),
+                                "algorithmic_GFLOP": round(plan.flops / 1e9, 3)}
+        from ttgen import configs as C
+        pairs_bf = C.gen_batch_torch(C.SEED_BATCH, d["shapes"], "cuda", torch.bfloat16)
+        plan_bf = ttc.BatchPlan(pairs_bf)
+        ib, jb = plan_bf.outputs()
+        bf_ms = timeit(lambda: plan_bf.run(ib, jb), reps=5)
+        beside["batch_bf16"] = {"batched_ms": round(bf_ms, 4),
+                                "contractions_per_s": round(8192 / (bf_ms * 1e-3), 1),
+                                "GBs": round(plan_bf.bytes / (bf_ms * 1e-3) / 1e9, 1),
+                                "algorithmic_GB": round(plan_bf.bytes / 1e9, 3)}
+        del pairs_bf, plan_bf, ib, jb
+    if "layer4" in parts:
+        d = W["layer4"]
+
+        def layer(prec):
+            Y = ttc.ttm_apply_dense(d["w"], d["X"], prec=prec)
+            _, dY = ttc.ttc_mse_loss(Y, d["T"])
+            ttc.ttm_apply_dense_bwd(d["w"], d["X"], dY, prec=prec)
+
+        for prec in ("bf16",):
+            layer(prec)
+            torch.cuda.synchronize()
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            for _ in range(3):
+                layer(prec)
+            b.record(stream)
+            torch.cuda.synchronize()
+            beside[f"layer4_{prec}_fwd_bwd_ms"] = round(a.elapsed_time(b) / 3, 4)
+        beside["layer4_f32_fwd_bwd_ms"] = round(part_ms["layer4"], 4)
+        beside["layer4_f32_fwd_ms"] = round(fwd_ms, 4)
+
+    line = {
+        "metric": "TT contractions/s + achieved GB/s or TFLOP/s vs roofline; fwd+bwd ms, plain vs batched",
+        "value": round(n_contr / (ms_step * 1e-3), 2),
+        "unit": "TT contractions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 (mpo8: bf16 in, f32 acc)",
+        "data": "synthetic (seeded generator; shapes and distributions of the five workloads)",
+        "config": {"workload": "tt-hot-path: " + "+".join(parts),
+                   "contractions_per_step": {p: CONTRACTIONS[p] for p in parts},
+                   "parallelism": "single GPU"},
+        "roofline": roof,
+        "parts": parts_out,
+        "beside": beside,
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(W, n_contr)
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

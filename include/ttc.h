@@ -237,7 +237,7 @@ ttc_status tt_contract_inner_bwd(const ttc_tt* x, const ttc_tt* y, const double*
  *                   two positions, row-major FP32 at d_junction +
  *                   junction_offset[p] elements (offsets from
  *                   tt_batch_plan_info).
- * Pairs need order >= 2 (SUFFIX2: >= 3) and order <= 64; X and Y of a pair
+ * Pairs need order >= 2 (SUFFIX2: >= 3) and order <= 32; X and Y of a pair
  * share dtype (FP32 or BF16) and mode sizes.  The plan copies every
  * descriptor (shapes and core pointers) when it is created; the core buffers
  * must stay alive and unchanged in place until the plan is destroyed.

@@ -1,0 +1,488 @@
+// Host side of the batched sweep: validation, cost model, longest-first
+// assignment of pairs to persistent workgroups, descriptor upload, launch
+// shape selection by timing (the autotuner), HIP-graph capture and replay,
+// and the per-pair launch loop used as the unbatched reference.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <functional>
+#include <map>
+#include <mutex>
+#include <queue>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "ttc_batch.h"
+
+namespace ttc {
+ttc_status fail(ttc_status s, const std::string& msg);
+}
+using namespace ttc;
+
+#define TTC_TRY(expr)            \
+  do {                           \
+    ttc_status _s = (expr);      \
+    if (_s != TTC_OK) return _s; \
+  } while (0)
+#define TTC_HIP(expr)                                                                                    \
+  do {                                                                                                   \
+    hipError_t _e = (expr);                                                                              \
+    if (_e != hipSuccess) return fail(TTC_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+  } while (0)
+
+struct PairHost {
+  int order;
+  std::vector<int> modes, rx, ry;
+  std::vector<void*> xc, yc;
+};
+
+// One launch shape: workgroup size and workgroups per compute unit.
+struct LaunchCfg {
+  int threads = 512;
+  int per_cu = 1;
+};
+
+struct ttc_plan {
+  int n = 0;
+  uint32_t ops = 0;
+  ttc_dtype dt = TTC_F32;
+  int device = 0;
+  int cus = 256;
+  std::vector<PairHost> pairs;
+  std::vector<int64_t> joff;
+  std::vector<double> cost;
+  double flops = 0, bytes = 0;
+  long max_rp = 1, max_t = 1;
+  // device memory (one allocation)
+  void* dmem = nullptr;
+  PairDev* d_pairs = nullptr;
+  int* d_ipool = nullptr;
+  void** d_ppool = nullptr;
+  int* d_begin = nullptr;   // per configuration, rebuilt on selection
+  int* d_order = nullptr;
+  int* d_ident = nullptr;   // 0..n-1 (per-pair launches)
+  int* d_01 = nullptr;      // {0, 1}
+  float* d_iface = nullptr;
+  float* d_tbuf = nullptr;
+  int max_grid = 0;
+  // selected launch
+  LaunchCfg cfg;
+  int grid = 0;
+  int lds_elems = 0;
+  // graph
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  double* g_inner = nullptr;
+  float* g_junc = nullptr;
+};
+
+namespace {
+
+// dynamic LDS per workgroup: the CU's 160 KB split between co-resident
+// workgroups, less room for the kernel's static LDS
+const int kLdsBytes = 156 * 1024;
+int lds_bytes_for(int per_cu) { return (160 * 1024) / per_cu - 4 * 1024; }
+
+ttc_status check_pair_desc(const ttc_pair& p, int idx, uint32_t ops, ttc_dtype* dt) {
+  const ttc_tt* ts[2] = {&p.x, &p.y};
+  for (int s = 0; s < 2; ++s) {
+    const ttc_tt* t = ts[s];
+    const std::string nm = "pair " + std::to_string(idx) + (s ? " y" : " x");
+    if (t->order < 2 || t->order > TTC_MAX_ORDER) return fail(TTC_ERR_SHAPE, nm + ": order outside [2, 32]");
+    if (!t->modes || !t->ranks || !t->cores) return fail(TTC_ERR_NULL, nm + ": NULL descriptor array");
+    if (t->dtype != TTC_F32 && t->dtype != TTC_BF16) return fail(TTC_ERR_DTYPE, nm + ": batched pairs are FP32 or BF16");
+    if (t->ranks[0] != 1 || t->ranks[t->order] != 1) return fail(TTC_ERR_RANK, nm + ": boundary ranks must be 1");
+    for (int k = 0; k < t->order; ++k) {
+      if (t->modes[k] < 1 || t->ranks[k] < 1) return fail(TTC_ERR_SHAPE, nm + ": bad shape");
+      if (!t->cores[k]) return fail(TTC_ERR_NULL, nm + ": NULL core pointer");
+    }
+  }
+  if (p.x.order != p.y.order) return fail(TTC_ERR_SHAPE, "pair " + std::to_string(idx) + ": orders differ");
+  if (p.x.dtype != p.y.dtype) return fail(TTC_ERR_DTYPE, "pair " + std::to_string(idx) + ": dtypes differ");
+  for (int k = 0; k < p.x.order; ++k)
+    if (p.x.modes[k] != p.y.modes[k]) return fail(TTC_ERR_SHAPE, "pair " + std::to_string(idx) + ": modes differ");
+  if ((ops & TTC_OP_SUFFIX2) && p.x.order < 3)
+    return fail(TTC_ERR_SHAPE, "pair " + std::to_string(idx) + ": SUFFIX2 needs order >= 3");
+  if (idx == 0) *dt = p.x.dtype;
+  else if (*dt != p.x.dtype) return fail(TTC_ERR_DTYPE, "all pairs must share one dtype");
+  return TTC_OK;
+}
+
+// Minimum-order FLOPs of one right-to-left step on core k.
+double step_flops(const PairHost& p, int k) {
+  const double I = p.modes[k], Rp = p.rx[k], Rn = p.rx[k + 1], Pp = p.ry[k], Pn = p.ry[k + 1];
+  const double a = 2 * I * Rp * Pn * (Rn + Pp);
+  const double b = 2 * I * Rn * Pp * (Pn + Rp);
+  return std::min(a, b);
+}
+
+// FLOPs the kernel executes on core k (its fixed order).
+double step_flops_exec(const PairHost& p, int k) {
+  const double I = p.modes[k], Rp = p.rx[k], Rn = p.rx[k + 1], Pp = p.ry[k], Pn = p.ry[k + 1];
+  return 2 * I * Rp * Pn * (Rn + Pp);
+}
+
+// Static longest-processing-time assignment: pairs sorted by cost, each
+// given to the currently least-loaded workgroup.  Returns CSR lists.
+void lpt_assign(const std::vector<double>& cost, int grid, std::vector<int>* begin, std::vector<int>* order) {
+  const int n = (int)cost.size();
+  std::vector<int> idx(n);
+  for (int i = 0; i < n; ++i) idx[i] = i;
+  std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+  typedef std::pair<double, int> Load;
+  std::priority_queue<Load, std::vector<Load>, std::greater<Load>> heap;
+  for (int g = 0; g < grid; ++g) heap.push(Load(0.0, g));
+  std::vector<std::vector<int>> lists(grid);
+  for (int i : idx) {
+    Load l = heap.top();
+    heap.pop();
+    lists[l.second].push_back(i);
+    l.first += cost[i];
+    heap.push(l);
+  }
+  begin->assign(grid + 1, 0);
+  order->clear();
+  for (int g = 0; g < grid; ++g) {
+    (*begin)[g] = (int)order->size();
+    order->insert(order->end(), lists[g].begin(), lists[g].end());
+  }
+  (*begin)[grid] = (int)order->size();
+}
+
+BatchArgs make_args(ttc_plan* P, const int* begin, const int* order, double* inner, float* junc, int lds_elems,
+                    int grid) {
+  BatchArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.pairs = P->d_pairs;
+  a.ipool = P->d_ipool;
+  a.ppool = P->d_ppool;
+  a.wg_begin = begin;
+  a.order = order;
+  a.ops = P->ops;
+  a.lds_elems = lds_elems;
+  a.iface = P->d_iface;
+  a.iface_stride = 2 * P->max_rp;
+  a.tbuf = P->d_tbuf;
+  a.t_stride = P->max_t;
+  a.inner = inner;
+  a.junction = junc;
+  (void)grid;
+  return a;
+}
+
+ttc_status upload_assignment(ttc_plan* P, const LaunchCfg& c, int* grid_out, int* lds_out) {
+  const int grid = std::min(P->cus * c.per_cu, std::max(P->n, 1));
+  std::vector<int> begin, order;
+  lpt_assign(P->cost, grid, &begin, &order);
+  TTC_HIP(hipMemcpy(P->d_begin, begin.data(), begin.size() * sizeof(int), hipMemcpyHostToDevice));
+  TTC_HIP(hipMemcpy(P->d_order, order.data(), order.size() * sizeof(int), hipMemcpyHostToDevice));
+  *grid_out = grid;
+  *lds_out = lds_bytes_for(c.per_cu) / (int)sizeof(float);
+  return TTC_OK;
+}
+
+std::string cache_key(const ttc_plan* P) {
+  uint64_t h = 1469598103934665603ULL;
+  auto mix = [&](uint64_t v) {
+    h ^= v;
+    h *= 1099511628211ULL;
+  };
+  for (const PairHost& p : P->pairs) {
+    mix(p.order);
+    for (int v : p.modes) mix(v);
+    for (int v : p.rx) mix(v);
+    for (int v : p.ry) mix(v);
+  }
+  mix(P->ops);
+  mix(P->dt);
+  std::ostringstream os;
+  os << "gfx950|abi" << TTC_ABI_VERSION << "|" << std::hex << h;
+  return os.str();
+}
+
+// Tiny persistent cache: one "key threads per_cu" line per entry.
+std::mutex g_cache_mu;
+bool cache_lookup(const std::string& key, LaunchCfg* c) {
+  const char* path = std::getenv("TTC_AUTOTUNE_CACHE");
+  if (!path) return false;
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  std::ifstream f(path);
+  std::string k;
+  int t, pc;
+  while (f >> k >> t >> pc)
+    if (k == key) {
+      c->threads = t;
+      c->per_cu = pc;
+      return true;
+    }
+  return false;
+}
+void cache_store(const std::string& key, const LaunchCfg& c) {
+  const char* path = std::getenv("TTC_AUTOTUNE_CACHE");
+  if (!path) return;
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  std::ofstream f(path, std::ios::app);
+  f << key << " " << c.threads << " " << c.per_cu << "\n";
+}
+
+ttc_status autotune(ttc_plan* P) {
+  const std::string key = cache_key(P);
+  LaunchCfg best;
+  if (cache_lookup(key, &best)) {
+    P->cfg = best;
+    return upload_assignment(P, best, &P->grid, &P->lds_elems);
+  }
+  const LaunchCfg cands[] = {{512, 1}, {256, 1}, {512, 2}, {256, 2}};
+  double* d_inner = nullptr;
+  float* d_junc = nullptr;
+  TTC_HIP(hipMalloc(&d_inner, sizeof(double) * std::max(P->n, 1)));
+  TTC_HIP(hipMalloc(&d_junc, sizeof(float) * std::max<int64_t>(P->joff.back(), 1)));
+  hipEvent_t e0, e1;
+  TTC_HIP(hipEventCreate(&e0));
+  TTC_HIP(hipEventCreate(&e1));
+  float best_ms = 1e30f;
+  for (const LaunchCfg& c : cands) {
+    int grid, lds;
+    TTC_TRY(upload_assignment(P, c, &grid, &lds));
+    BatchArgs a = make_args(P, P->d_begin, P->d_order, d_inner, d_junc, lds, grid);
+    TTC_HIP(launch_batch(P->dt, a, grid, c.threads, 0));
+    TTC_HIP(hipEventRecord(e0, 0));
+    for (int r = 0; r < 2; ++r) TTC_HIP(launch_batch(P->dt, a, grid, c.threads, 0));
+    TTC_HIP(hipEventRecord(e1, 0));
+    TTC_HIP(hipEventSynchronize(e1));
+    float ms = 0;
+    TTC_HIP(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = c;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(d_inner);
+  (void)hipFree(d_junc);
+  P->cfg = best;
+  cache_store(key, best);
+  return upload_assignment(P, best, &P->grid, &P->lds_elems);
+}
+
+void release(ttc_plan* P) {
+  if (P->exec) (void)hipGraphExecDestroy(P->exec);
+  if (P->graph) (void)hipGraphDestroy(P->graph);
+  if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
+  if (P->dmem) (void)hipFree(P->dmem);
+  P->exec = nullptr;
+  P->graph = nullptr;
+  P->cap_stream = nullptr;
+  P->dmem = nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+ttc_status tt_batch_plan_create(const ttc_pair* pairs, int32_t n, uint32_t ops, ttc_prec prec, ttc_plan** plan) {
+  if (!plan) return fail(TTC_ERR_NULL, "plan is NULL");
+  *plan = nullptr;
+  if (!pairs || n < 1) return fail(TTC_ERR_NULL, "no pairs");
+  if (ops == 0 || (ops & ~(TTC_OP_INNER | TTC_OP_SUFFIX2))) return fail(TTC_ERR_UNSUPPORTED, "bad ops mask");
+  if (prec != TTC_PREC_AUTO && prec != TTC_PREC_F32) return fail(TTC_ERR_UNSUPPORTED, "batched precision is FP32");
+  ttc_dtype dt = TTC_F32;
+  for (int i = 0; i < n; ++i) TTC_TRY(check_pair_desc(pairs[i], i, ops, &dt));
+  ttc_plan* P = new ttc_plan();
+  P->n = n;
+  P->ops = ops;
+  P->dt = dt;
+  const size_t esz = dt == TTC_BF16 ? 2 : 4;
+  P->pairs.resize(n);
+  P->joff.assign(n + 1, 0);
+  P->cost.assign(n, 0.0);
+  std::vector<PairDev> pd(n);
+  std::vector<int> ipool;
+  std::vector<void*> ppool;
+  for (int i = 0; i < n; ++i) {
+    PairHost& h = P->pairs[i];
+    const ttc_tt& x = pairs[i].x;
+    const ttc_tt& y = pairs[i].y;
+    const int N = x.order;
+    h.order = N;
+    h.modes.assign(x.modes, x.modes + N);
+    h.rx.assign(x.ranks, x.ranks + N + 1);
+    h.ry.assign(y.ranks, y.ranks + N + 1);
+    h.xc.assign(x.cores, x.cores + N);
+    h.yc.assign(y.cores, y.cores + N);
+    pd[i].order = N;
+    pd[i].ibase = (int)ipool.size();
+    pd[i].pbase = (int)ppool.size();
+    pd[i].pad = 0;
+    pd[i].jout = P->joff[i];
+    ipool.insert(ipool.end(), h.modes.begin(), h.modes.end());
+    ipool.insert(ipool.end(), h.rx.begin(), h.rx.end());
+    ipool.insert(ipool.end(), h.ry.begin(), h.ry.end());
+    ppool.insert(ppool.end(), h.xc.begin(), h.xc.end());
+    ppool.insert(ppool.end(), h.yc.begin(), h.yc.end());
+    P->joff[i + 1] = P->joff[i] + ((ops & TTC_OP_SUFFIX2) ? (int64_t)h.rx[N - 2] * h.ry[N - 2] : 0);
+    double fl = 0, fl_exec = 0, by = 0;
+    for (int k = 1; k < N; ++k) {
+      fl += step_flops(h, k);
+      fl_exec += step_flops_exec(h, k);
+    }
+    fl += 2.0 * h.modes[0] * h.rx[1] * h.ry[1] + 2.0 * h.rx[1] * h.ry[1];
+    fl_exec += 2.0 * h.modes[0] * h.rx[1] * h.ry[1];
+    for (int k = 0; k < N; ++k)
+      by += (double)esz * ((double)h.rx[k] * h.modes[k] * h.rx[k + 1] + (double)h.ry[k] * h.modes[k] * h.ry[k + 1]);
+    by += (ops & TTC_OP_INNER) ? 8.0 : 0.0;
+    by += 4.0 * (double)(P->joff[i + 1] - P->joff[i]);
+    P->flops += fl;
+    P->bytes += by;
+    P->cost[i] = fl_exec + 16.0 * by;  // FLOPs plus memory time at ~16 FLOP/byte
+    for (int b = 1; b <= N; ++b) P->max_rp = std::max<long>(P->max_rp, (long)h.rx[b] * h.ry[b]);
+    for (int k = 1; k < N; ++k) P->max_t = std::max<long>(P->max_t, (long)h.rx[k] * h.ry[k + 1]);
+  }
+  hipError_t e = hipGetDevice(&P->device);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&P->cus, hipDeviceAttributeMultiprocessorCount, P->device);
+  if (e != hipSuccess) {
+    delete P;
+    return fail(TTC_ERR_HIP, std::string("device query: ") + hipGetErrorString(e));
+  }
+  P->max_grid = P->cus * 2;
+  // one device allocation for every table
+  auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  size_t off = 0;
+  const size_t o_pairs = off;
+  off += al(sizeof(PairDev) * n);
+  const size_t o_ipool = off;
+  off += al(sizeof(int) * ipool.size());
+  const size_t o_ppool = off;
+  off += al(sizeof(void*) * ppool.size());
+  const size_t o_begin = off;
+  off += al(sizeof(int) * (P->max_grid + 1));
+  const size_t o_order = off;
+  off += al(sizeof(int) * n);
+  const size_t o_ident = off;
+  off += al(sizeof(int) * n);
+  const size_t o_01 = off;
+  off += al(sizeof(int) * 2);
+  const size_t o_iface = off;
+  off += al(sizeof(float) * 2 * P->max_rp * P->max_grid);
+  const size_t o_tbuf = off;
+  off += al(sizeof(float) * P->max_t * P->max_grid);
+  e = hipMalloc(&P->dmem, off);
+  if (e != hipSuccess) {
+    delete P;
+    return fail(TTC_ERR_HIP, std::string("plan allocation: ") + hipGetErrorString(e));
+  }
+  char* base = (char*)P->dmem;
+  P->d_pairs = (PairDev*)(base + o_pairs);
+  P->d_ipool = (int*)(base + o_ipool);
+  P->d_ppool = (void**)(base + o_ppool);
+  P->d_begin = (int*)(base + o_begin);
+  P->d_order = (int*)(base + o_order);
+  P->d_ident = (int*)(base + o_ident);
+  P->d_01 = (int*)(base + o_01);
+  P->d_iface = (float*)(base + o_iface);
+  P->d_tbuf = (float*)(base + o_tbuf);
+  std::vector<int> ident(n);
+  for (int i = 0; i < n; ++i) ident[i] = i;
+  const int zo[2] = {0, 1};
+  ttc_status st = TTC_OK;
+  auto cp = [&](void* dst, const void* src, size_t b) {
+    if (st == TTC_OK && b) {
+      hipError_t ee = hipMemcpy(dst, src, b, hipMemcpyHostToDevice);
+      if (ee != hipSuccess) st = fail(TTC_ERR_HIP, std::string("descriptor upload: ") + hipGetErrorString(ee));
+    }
+  };
+  cp(P->d_pairs, pd.data(), sizeof(PairDev) * n);
+  cp(P->d_ipool, ipool.data(), sizeof(int) * ipool.size());
+  cp(P->d_ppool, ppool.data(), sizeof(void*) * ppool.size());
+  cp(P->d_ident, ident.data(), sizeof(int) * n);
+  cp(P->d_01, zo, sizeof(zo));
+  if (st == TTC_OK) {
+    hipError_t ee = batch_set_lds(kLdsBytes);
+    if (ee != hipSuccess) st = fail(TTC_ERR_HIP, std::string("kernel attribute: ") + hipGetErrorString(ee));
+  }
+  if (st == TTC_OK) st = autotune(P);
+  if (st == TTC_OK) {
+    hipError_t ee = hipDeviceSynchronize();
+    if (ee != hipSuccess) st = fail(TTC_ERR_HIP, std::string("plan setup: ") + hipGetErrorString(ee));
+  }
+  if (st != TTC_OK) {
+    release(P);
+    delete P;
+    return st;
+  }
+  *plan = P;
+  return TTC_OK;
+}
+
+ttc_status tt_batch_plan_info(const ttc_plan* P, int64_t* junction_offsets, double* flops, double* bytes) {
+  if (!P) return fail(TTC_ERR_NULL, "plan is NULL");
+  if (junction_offsets) std::memcpy(junction_offsets, P->joff.data(), sizeof(int64_t) * (P->n + 1));
+  if (flops) *flops = P->flops;
+  if (bytes) *bytes = P->bytes;
+  return TTC_OK;
+}
+
+ttc_status tt_batch_run(ttc_plan* P, double* d_inner, float* d_junction, void* stream) {
+  if (!P) return fail(TTC_ERR_NULL, "plan is NULL");
+  if ((P->ops & TTC_OP_INNER) && !d_inner) return fail(TTC_ERR_NULL, "d_inner is NULL");
+  if ((P->ops & TTC_OP_SUFFIX2) && !d_junction) return fail(TTC_ERR_NULL, "d_junction is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  BatchArgs a = make_args(P, P->d_begin, P->d_order, d_inner, d_junction, P->lds_elems, P->grid);
+  if (!s) {
+    TTC_HIP(launch_batch(P->dt, a, P->grid, P->cfg.threads, s));
+    return TTC_OK;
+  }
+  if (!P->exec || P->g_inner != d_inner || P->g_junc != d_junction) {
+    if (P->exec) {
+      (void)hipGraphExecDestroy(P->exec);
+      P->exec = nullptr;
+    }
+    if (P->graph) {
+      (void)hipGraphDestroy(P->graph);
+      P->graph = nullptr;
+    }
+    if (!P->cap_stream) TTC_HIP(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking));
+    TTC_HIP(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal));
+    hipError_t le = launch_batch(P->dt, a, P->grid, P->cfg.threads, P->cap_stream);
+    hipGraph_t g = nullptr;
+    hipError_t ce = hipStreamEndCapture(P->cap_stream, &g);
+    if (le != hipSuccess) return fail(TTC_ERR_HIP, std::string("capture launch: ") + hipGetErrorString(le));
+    if (ce != hipSuccess) return fail(TTC_ERR_HIP, std::string("end capture: ") + hipGetErrorString(ce));
+    P->graph = g;
+    TTC_HIP(hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0));
+    P->g_inner = d_inner;
+    P->g_junc = d_junction;
+  }
+  TTC_HIP(hipGraphLaunch(P->exec, s));
+  return TTC_OK;
+}
+
+ttc_status tt_batch_run_plain(ttc_plan* P, double* d_inner, float* d_junction, void* stream) {
+  if (!P) return fail(TTC_ERR_NULL, "plan is NULL");
+  if ((P->ops & TTC_OP_INNER) && !d_inner) return fail(TTC_ERR_NULL, "d_inner is NULL");
+  if ((P->ops & TTC_OP_SUFFIX2) && !d_junction) return fail(TTC_ERR_NULL, "d_junction is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  const int lds = kLdsBytes / (int)sizeof(float);
+  for (int p = 0; p < P->n; ++p) {
+    BatchArgs a = make_args(P, P->d_01, P->d_ident + p, d_inner, d_junction, lds, 1);
+    TTC_HIP(launch_batch(P->dt, a, 1, 512, s));
+  }
+  return TTC_OK;
+}
+
+void tt_batch_plan_destroy(ttc_plan* P) {
+  if (!P) return;
+  (void)hipDeviceSynchronize();
+  release(P);
+  delete P;
+}
+
+}  // extern "C"

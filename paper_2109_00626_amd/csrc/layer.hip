@@ -1,0 +1,392 @@
+// TT-matrix times a dense batch (a TT layer), its backward, and the MSE loss.
+//
+// Dense schedule: the TT-matrix is rebuilt from its cores by a chain of
+// matrix products L_{k+1} = L_k . W^(k) (W^(k) viewed as R_k x (I_k J_k R_{k+1})),
+// whose result indexes the pair modes m_k = (i_k, j_k) with m_0 slowest; a
+// permutation then gives W[i, j] with little-endian row and column indices.
+// The batch product is one MFMA GEMM.  The backward forms dW = dY^T X,
+// permutes it back to pair-mode order and projects it onto each core:
+//   dG^(k)[r, m_k, s] = sum_{m_<k} L_k[m_<k, r] Rt_k[m_<k, m_k, s],
+// with the right environments Rt_{k-1} = Rt_k . W^(k)^T (Rt_{N-1} = dW).
+// Every contraction is the GEMM kernel below.
+//
+// GEMM: 128 x 128 output tile per 256-thread workgroup, each wave a 64 x 64
+// quarter on 16x16 MFMA tiles (FP32: 16x16x4, BF16: 16x16x32 with FP32
+// accumulation), operands staged through double-buffered LDS.  Global
+// operands are FP32; the BF16 variant rounds them (RNE) while staging.
+// Optional split-K writes FP32 partial slabs that a second kernel sums in a
+// fixed order (deterministic).
+#include "ttc_device.hpp"
+#include "ttc_layer.h"
+
+namespace ttc {
+
+#define GBM 128
+#define GBN 128
+#define GPAD 4
+
+template <bool BF16>
+struct GemmCfg;
+template <>
+struct GemmCfg<false> {
+  static constexpr int BK = 32;
+};
+template <>
+struct GemmCfg<true> {
+  static constexpr int BK = 64;
+};
+
+// Number of float4 loads per thread for one operand tile.
+template <bool BF16>
+__device__ constexpr int loads_per_thread() {
+  return (GBM * GemmCfg<BF16>::BK / 4) / 256;
+}
+
+// Load one operand tile (rows = the operand's M or N dimension, 128 of them;
+// columns = 32/64 of K) into registers.  kc: K is the contiguous dimension.
+template <bool BF16, bool KC>
+__device__ __forceinline__ void load_tile(const float* P, long ld, int row0, int nrows, int k0, int K, bool vec,
+                                          f32x4* r) {
+  constexpr int BK = GemmCfg<BF16>::BK;
+  constexpr int L = loads_per_thread<BF16>();
+#pragma unroll
+  for (int it = 0; it < L; ++it) {
+    const int e = threadIdx.x + 256 * it;
+    int row, kk;
+    if (KC) {
+      row = e / (BK / 4);
+      kk = (e % (BK / 4)) * 4;
+    } else {
+      kk = e / (GBM / 4);
+      row = (e % (GBM / 4)) * 4;
+    }
+    f32x4 v = {0.f, 0.f, 0.f, 0.f};
+    if (KC) {
+      const int gr = row0 + row, gk = k0 + kk;
+      if (gr < nrows) {
+        const float* p = P + (long)gr * ld + gk;
+        if (vec && gk + 3 < K) {
+          v = *reinterpret_cast<const f32x4*>(p);
+        } else {
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            if (gk + q < K) v[q] = p[q];
+        }
+      }
+    } else {
+      const int gr = row0 + row, gk = k0 + kk;
+      if (gk < K) {
+        const float* p = P + (long)gk * ld + gr;
+        if (vec && gr + 3 < nrows) {
+          v = *reinterpret_cast<const f32x4*>(p);
+        } else {
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            if (gr + q < nrows) v[q] = p[q];
+        }
+      }
+    }
+    r[it] = v;
+  }
+}
+
+// Store staged registers into LDS.  FP32 layout: S[k][row] (pitch GBM+GPAD);
+// BF16 layout: S[row][k] (pitch BK+8, k contiguous for 16-byte fragments).
+template <bool BF16, bool KC>
+__device__ __forceinline__ void store_tile(void* S, const f32x4* r) {
+  constexpr int BK = GemmCfg<BF16>::BK;
+  constexpr int L = loads_per_thread<BF16>();
+#pragma unroll
+  for (int it = 0; it < L; ++it) {
+    const int e = threadIdx.x + 256 * it;
+    int row, kk;
+    if (KC) {
+      row = e / (BK / 4);
+      kk = (e % (BK / 4)) * 4;
+    } else {
+      kk = e / (GBM / 4);
+      row = (e % (GBM / 4)) * 4;
+    }
+    if (!BF16) {
+      float* s = reinterpret_cast<float*>(S);
+      if (KC) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) s[(kk + q) * (GBM + GPAD) + row] = r[it][q];
+      } else {
+        *reinterpret_cast<f32x4*>(s + kk * (GBM + GPAD) + row) = r[it];
+      }
+    } else {
+      uint16_t* s = reinterpret_cast<uint16_t*>(S);
+      constexpr int P = BK + 8;
+      if (KC) {
+        uint2 w;
+        w.x = (uint32_t)f32_to_bf16(r[it][0]) | ((uint32_t)f32_to_bf16(r[it][1]) << 16);
+        w.y = (uint32_t)f32_to_bf16(r[it][2]) | ((uint32_t)f32_to_bf16(r[it][3]) << 16);
+        *reinterpret_cast<uint2*>(s + row * P + kk) = w;
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) s[(row + q) * P + kk] = f32_to_bf16(r[it][q]);
+      }
+    }
+  }
+}
+
+template <bool BF16>
+__host__ __device__ constexpr int tile_elems() {
+  return BF16 ? GBM * (GemmCfg<true>::BK + 8) : GemmCfg<false>::BK * (GBM + GPAD);
+}
+
+template <bool A_KC, bool B_KC, bool BF16>
+__global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int BK = GemmCfg<BF16>::BK;
+  constexpr int L = loads_per_thread<BF16>();
+  constexpr int esz = BF16 ? 2 : 4;
+  constexpr int TE = tile_elems<BF16>();
+  unsigned char* As = smem;                    // [2][TE]
+  unsigned char* Bs = smem + 2 * TE * esz;     // [2][TE]
+  const int tn = (g.N + GBN - 1) / GBN;
+  const int bm = blockIdx.x / tn, bn = blockIdx.x - bm * tn;
+  const int m0 = bm * GBM, n0 = bn * GBN;
+  // K range of this split
+  const int kper = ((g.K + g.splits - 1) / g.splits + BK - 1) / BK * BK;
+  const int kbeg = blockIdx.y * kper;
+  const int kend = min(g.K, kbeg + kper);
+  const int nk = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
+
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int li = lane & 15, lg = lane >> 4;
+  f32x4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  f32x4 ra[L], rb[L];
+  if (nk > 0) {
+    load_tile<BF16, A_KC>(g.A, g.lda, m0, g.M, kbeg, kend, g.vec_a, ra);
+    load_tile<BF16, B_KC>(g.B, g.ldb, n0, g.N, kbeg, kend, g.vec_b, rb);
+    store_tile<BF16, A_KC>(As, ra);
+    store_tile<BF16, B_KC>(Bs, rb);
+  }
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) {
+      const int k0 = kbeg + (kt + 1) * BK;
+      load_tile<BF16, A_KC>(g.A, g.lda, m0, g.M, k0, kend, g.vec_a, ra);
+      load_tile<BF16, B_KC>(g.B, g.ldb, n0, g.N, k0, kend, g.vec_b, rb);
+    }
+    if (!BF16) {
+      const float* a_s = reinterpret_cast<const float*>(As) + buf * TE;
+      const float* b_s = reinterpret_cast<const float*>(Bs) + buf * TE;
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += 4) {
+        float av[4], bv[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) av[i] = a_s[(kk + lg) * (GBM + GPAD) + wm * 64 + 16 * i + li];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) bv[j] = b_s[(kk + lg) * (GBM + GPAD) + wn * 64 + 16 * j + li];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc[i][j], 0, 0, 0);
+      }
+    } else {
+      const uint16_t* a_s = reinterpret_cast<const uint16_t*>(As) + buf * TE;
+      const uint16_t* b_s = reinterpret_cast<const uint16_t*>(Bs) + buf * TE;
+      constexpr int P = BK + 8;
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += 32) {
+        bf16x8 av[4], bv[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          av[i] = *reinterpret_cast<const bf16x8*>(a_s + (wm * 64 + 16 * i + li) * P + kk + 8 * lg);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          bv[j] = *reinterpret_cast<const bf16x8*>(b_s + (wn * 64 + 16 * j + li) * P + kk + 8 * lg);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv[j], acc[i][j], 0, 0, 0);
+      }
+    }
+    if (kt + 1 < nk) {
+      store_tile<BF16, A_KC>(As + (buf ^ 1) * TE * esz, ra);
+      store_tile<BF16, B_KC>(Bs + (buf ^ 1) * TE * esz, rb);
+    }
+    __syncthreads();
+  }
+  float* C = g.splits > 1 ? g.slab + (long)blockIdx.y * g.M * g.N : g.C;
+  const long ldc = g.splits > 1 ? g.N : g.ldc;
+  const float alpha = g.splits > 1 ? 1.f : g.alpha;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int m = m0 + wm * 64 + 16 * i + 4 * lg + v;
+        const int n = n0 + wn * 64 + 16 * j + li;
+        if (m < g.M && n < g.N) C[(long)m * ldc + n] = alpha * acc[i][j][v];
+      }
+}
+
+// C = alpha * sum over slabs, fixed order.
+__global__ __launch_bounds__(256) void splitk_reduce_kernel(const float* slab, int splits, int M, int N, float alpha,
+                                                            float* C, long ldc) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long MN = (long)M * N;
+  if (e >= MN) return;
+  float s = 0.f;
+  for (int z = 0; z < splits; ++z) s += slab[(long)z * MN + e];
+  const long m = e / N, n = e - m * N;
+  C[m * ldc + n] = alpha * s;
+}
+
+// Pair-mode order (m_0 slowest, m_k = i_k * J_k + j_k) <-> W[i, j] with
+// little-endian i and j.  dir 0: pair -> matrix, dir 1: matrix -> pair.
+// One thread per element of the destination.
+__global__ __launch_bounds__(256) void permute_kernel(PermArgs p) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= p.total) return;
+  long src;
+  if (p.dir == 0) {
+    // destination: matrix element (row, col)
+    long row = e / p.cols, col = e - row * p.cols;
+    long off = 0;
+    for (int k = 0; k < p.d; ++k) {
+      const int ik = (int)(row % p.I[k]);
+      row /= p.I[k];
+      const int jk = (int)(col % p.J[k]);
+      col /= p.J[k];
+      off += (long)(ik * p.J[k] + jk) * p.pstride[k];
+    }
+    src = off;
+  } else {
+    // destination: pair-mode element e
+    long rem = e, row = 0, col = 0;
+    long rs = 1, cs = 1;
+    // digits from the fastest pair mode (k = d-1) to the slowest
+    long ris[TTC_MAX_ORDER], cjs[TTC_MAX_ORDER];
+    for (int k = p.d - 1; k >= 0; --k) {
+      const int mk = (int)(rem % (p.I[k] * p.J[k]));
+      rem /= (p.I[k] * p.J[k]);
+      ris[k] = mk / p.J[k];
+      cjs[k] = mk - ris[k] * p.J[k];
+    }
+    for (int k = 0; k < p.d; ++k) {
+      row += ris[k] * rs;
+      rs *= p.I[k];
+      col += cjs[k] * cs;
+      cs *= p.J[k];
+    }
+    src = row * p.cols + col;
+  }
+  p.dst[e] = p.src[src];
+}
+
+// Partial sums of (y - t)^2 per block and dy = scale * (y - t); the
+// difference, its square and the sum are FP64.
+__global__ __launch_bounds__(256) void mse_partial_kernel(const float* y, const float* t, long n, float* dy,
+                                                          double dscale, double* partials) {
+  __shared__ double scratch[16];
+  double s = 0.0;
+  const long stride = (long)gridDim.x * blockDim.x;
+  const long n4 = n / 4;
+  const f32x4* y4 = reinterpret_cast<const f32x4*>(y);
+  const f32x4* t4 = reinterpret_cast<const f32x4*>(t);
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n4; e += stride) {
+    const f32x4 a = y4[e], b = t4[e];
+    f32x4 g;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const double d = (double)a[q] - (double)b[q];
+      s += d * d;
+      g[q] = (float)(dscale * d);
+    }
+    if (dy) reinterpret_cast<f32x4*>(dy)[e] = g;
+  }
+  for (long e = 4 * n4 + (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
+    const double d = (double)y[e] - (double)t[e];
+    s += d * d;
+    if (dy) dy[e] = (float)(dscale * d);
+  }
+  s = wg_sum_f64(s, scratch);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(256) void mse_final_kernel(const double* partials, int nb, double inv_n, double* out) {
+  __shared__ double scratch[16];
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) s += partials[b];
+  s = wg_sum_f64(s, scratch);
+  if (threadIdx.x == 0) out[0] = s * inv_n;
+}
+
+// ------------------------------------------------------------------ launchers
+template <bool A_KC, bool B_KC, bool BF16>
+static hipError_t gemm_launch(const GemmArgs& g, hipStream_t s) {
+  constexpr int esz = BF16 ? 2 : 4;
+  const size_t lds = (size_t)4 * tile_elems<BF16>() * esz;
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm_kernel<A_KC, B_KC, BF16>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  const int tiles = ((g.M + GBM - 1) / GBM) * ((g.N + GBN - 1) / GBN);
+  hipLaunchKernelGGL((gemm_kernel<A_KC, B_KC, BF16>), dim3(tiles, g.splits), dim3(256), lds, s, g);
+  return hipGetLastError();
+}
+
+int gemm_bk(bool bf16) { return bf16 ? GemmCfg<true>::BK : GemmCfg<false>::BK; }
+
+hipError_t launch_gemm(bool a_kc, bool b_kc, bool bf16, const GemmArgs& g, hipStream_t s) {
+  if (g.M <= 0 || g.N <= 0) return hipSuccess;
+  hipError_t e;
+  const int idx = (a_kc ? 4 : 0) + (b_kc ? 2 : 0) + (bf16 ? 1 : 0);
+  switch (idx) {
+    case 0: e = gemm_launch<false, false, false>(g, s); break;
+    case 1: e = gemm_launch<false, false, true>(g, s); break;
+    case 2: e = gemm_launch<false, true, false>(g, s); break;
+    case 3: e = gemm_launch<false, true, true>(g, s); break;
+    case 4: e = gemm_launch<true, false, false>(g, s); break;
+    case 5: e = gemm_launch<true, false, true>(g, s); break;
+    case 6: e = gemm_launch<true, true, false>(g, s); break;
+    default: e = gemm_launch<true, true, true>(g, s); break;
+  }
+  if (e != hipSuccess || g.splits <= 1) return e;
+  const long MN = (long)g.M * g.N;
+  hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)((MN + 255) / 256)), dim3(256), 0, s, g.slab, g.splits,
+                     g.M, g.N, g.alpha, g.C, g.ldc);
+  return hipGetLastError();
+}
+
+hipError_t launch_permute(const PermArgs& p, hipStream_t s) {
+  if (p.total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(permute_kernel, dim3((unsigned)((p.total + 255) / 256)), dim3(256), 0, s, p);
+  return hipGetLastError();
+}
+
+int mse_blocks(long n) {
+  long b = (n / 4 + 255) / 256;
+  if (b < 1) b = 1;
+  if (b > 2048) b = 2048;
+  return (int)b;
+}
+
+hipError_t launch_mse(const float* y, const float* t, long n, float* dy, double* partials, double* out,
+                      hipStream_t s) {
+  const int nb = mse_blocks(n);
+  hipLaunchKernelGGL(mse_partial_kernel, dim3(nb), dim3(256), 0, s, y, t, n, dy, 2.0 / (double)n, partials);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(mse_final_kernel, dim3(1), dim3(256), 0, s, partials, nb, 1.0 / (double)n, out);
+  return hipGetLastError();
+}
+
+}  // namespace ttc

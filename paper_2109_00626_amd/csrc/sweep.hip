@@ -9,8 +9,8 @@
 // Right to left:
 //   V_k = sum_i G_x^(k)[:, i, :] V_{k+1} G_y^(k)[:, i, :]^T
 //   S_i = G_x^(k)[:, i, :] . V_{k+1};  V_k += sum_i S_i . G_y^(k)[:, i, :]^T
-// Interfaces live in LDS; the per-mode intermediate lives in LDS when it
-// fits, otherwise in a per-block slice of the caller's workspace.
+// Interfaces and the per-mode intermediate live in LDS when they fit,
+// otherwise in a per-block slice of the caller's workspace.
 #include "ttc_device.hpp"
 #include "ttc_internal.h"
 
@@ -104,9 +104,10 @@ __global__ __launch_bounds__(256) void sweep_kernel(SweepArgs a) {
   const int b = blockIdx.x;
   const int dir = a.dir[b];
   if (dir < 0) return;
-  Tc* bufA = reinterpret_cast<Tc*>(smem);
+  Tc* bufA = a.i_global ? reinterpret_cast<Tc*>(a.i_global) + b * a.i_stride : reinterpret_cast<Tc*>(smem);
   Tc* bufB = bufA + a.max_rp;
-  Tc* T = a.t_global ? reinterpret_cast<Tc*>(a.t_global) + b * a.t_stride : bufB + a.max_rp;
+  Tc* lds_free = a.i_global ? reinterpret_cast<Tc*>(smem) : bufB + a.max_rp;
+  Tc* T = a.t_global ? reinterpret_cast<Tc*>(a.t_global) + b * a.t_stride : lds_free;
   Tc* res = run_sweep<Tin, Tc>(a.x, a.y, dir, a.stop[b], bufA, bufB, T, a.tcap);
   const int n = a.x.ranks[a.stop[b]] * a.y.ranks[a.stop[b]];
   wg_copy<Tc>(reinterpret_cast<Tc*>(a.out[b]), res, n);
@@ -128,9 +129,10 @@ __global__ __launch_bounds__(256) void meet_kernel(const Tc* W, const Tc* V, int
 template <typename Tin, typename Tc>
 __global__ __launch_bounds__(256) void grad_ckpt_kernel(GradArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  Tc* bufA = reinterpret_cast<Tc*>(smem);
+  Tc* bufA = a.i_global ? reinterpret_cast<Tc*>(a.i_global) + blockIdx.x * a.i_stride : reinterpret_cast<Tc*>(smem);
   Tc* bufB = bufA + a.max_rp;
-  Tc* T = a.t_global ? reinterpret_cast<Tc*>(a.t_global) + blockIdx.x * a.t_stride : bufB + a.max_rp;
+  Tc* lds_free = a.i_global ? reinterpret_cast<Tc*>(smem) : bufB + a.max_rp;
+  Tc* T = a.t_global ? reinterpret_cast<Tc*>(a.t_global) + blockIdx.x * a.t_stride : lds_free;
   const int N = a.x.order, c = a.stride, ns = a.nseg;
   Tc* ckW = reinterpret_cast<Tc*>(a.ckW);
   Tc* ckV = reinterpret_cast<Tc*>(a.ckV);
@@ -173,9 +175,10 @@ __global__ __launch_bounds__(256) void grad_seg_kernel(GradArgs a) {
   const int s = blockIdx.x;
   const int N = a.x.order, c = a.stride;
   const int k0 = s * c, k1 = (k0 + c < N) ? k0 + c : N;
-  Tc* bufA = reinterpret_cast<Tc*>(smem);
+  Tc* bufA = a.i_global ? reinterpret_cast<Tc*>(a.i_global) + blockIdx.x * a.i_stride : reinterpret_cast<Tc*>(smem);
   Tc* bufB = bufA + a.max_rp;
-  Tc* T = a.t_global ? reinterpret_cast<Tc*>(a.t_global) + blockIdx.x * a.t_stride : bufB + a.max_rp;
+  Tc* lds_free = a.i_global ? reinterpret_cast<Tc*>(smem) : bufB + a.max_rp;
+  Tc* T = a.t_global ? reinterpret_cast<Tc*>(a.t_global) + blockIdx.x * a.t_stride : lds_free;
   Tc* segV = reinterpret_cast<Tc*>(a.segV) + (long)s * c * a.max_rp;  // slot k - k0 holds V_{k+1}
   const Tc* ckW = reinterpret_cast<const Tc*>(a.ckW) + (long)s * a.max_rp;
   const Tc* ckV = reinterpret_cast<const Tc*>(a.ckV) + (long)s * a.max_rp;

@@ -116,10 +116,14 @@ struct SweepSizing {
   int max_rp = 1;
   int tcap = 1;
   bool t_global = false;
+  bool i_global = false;
   size_t lds = 0;
   size_t t_block_bytes = 0;
+  size_t i_block_bytes = 0;
 };
 
+// Interfaces and the per-mode intermediate go to LDS when they fit; what
+// does not fit goes to a per-block slice of the workspace.
 ttc_status size_sweep(const ttc_tt* x, const ttc_tt* y, int k0, int k1, SweepSizing* out) {
   const size_t cs = comp_size(x->dtype);
   long max_rp = 1, max_t = 1, max_I = 1;
@@ -129,19 +133,25 @@ ttc_status size_sweep(const ttc_tt* x, const ttc_tt* y, int k0, int k1, SweepSiz
     max_I = std::max<long>(max_I, x->modes[k]);
   }
   const long budget = lds_limit_bytes() / (long)cs;
-  if (2 * max_rp > budget) return fail(TTC_ERR_UNSUPPORTED, "interface matrix larger than LDS (ranks too large)");
   SweepSizing s;
   s.max_rp = (int)max_rp;
-  if (2 * max_rp + max_t <= budget) {
-    s.tcap = (int)std::min(budget - 2 * max_rp, max_t * max_I);
-    s.t_global = false;
-    s.lds = (size_t)(2 * max_rp + s.tcap) * cs;
+  long lds_elems = 0;
+  if (2 * max_rp <= budget) {
+    lds_elems = 2 * max_rp;
+  } else {
+    s.i_global = true;
+    s.i_block_bytes = (size_t)(2 * max_rp) * cs;
+  }
+  const long left = budget - lds_elems;
+  if (left >= max_t) {
+    s.tcap = (int)std::min(left, max_t * max_I);
+    lds_elems += s.tcap;
   } else {
     s.tcap = (int)(max_t * std::min<long>(max_I, 8));
     s.t_global = true;
-    s.lds = (size_t)(2 * max_rp) * cs;
     s.t_block_bytes = (size_t)s.tcap * cs;
   }
+  s.lds = (size_t)lds_elems * cs;
   *out = s;
   return TTC_OK;
 }
@@ -215,6 +225,7 @@ ttc_status run_junction(const ttc_tt* x, const ttc_tt* y, BlockKind kind, int k,
   const int k0 = kind == BK_PREFIX ? 0 : k, k1 = kind == BK_PREFIX ? k : x->order;
   TTC_TRY(size_sweep(x, y, k0, k1, &sz));
   void* tg = sz.t_global ? ws.take(sz.t_block_bytes) : nullptr;
+  void* ig = sz.i_global ? ws.take(sz.i_block_bytes) : nullptr;
   if (sizing) return TTC_OK;
   if (ws.off > ws_bytes) return fail(TTC_ERR_WORKSPACE, "workspace too small");
   SweepArgs a;
@@ -229,6 +240,8 @@ ttc_status run_junction(const ttc_tt* x, const ttc_tt* y, BlockKind kind, int k,
   a.tcap = sz.tcap;
   a.t_global = tg;
   a.t_stride = sz.tcap;
+  a.i_global = ig;
+  a.i_stride = 2L * sz.max_rp;
   TTC_HIP(launch_sweep(x->dtype, a, 1, sz.lds, s));
   return TTC_OK;
 }
@@ -244,6 +257,7 @@ ttc_status run_inner(const ttc_tt* x, const ttc_tt* y, double* d_out, Arena& ws,
   SweepSizing sz;
   TTC_TRY(size_sweep(x, y, 0, N, &sz));
   void* tg = sz.t_global ? ws.take(2 * sz.t_block_bytes) : nullptr;
+  void* ig = sz.i_global ? ws.take(2 * sz.i_block_bytes) : nullptr;
   if (sizing) return TTC_OK;
   if (ws.off > ws_bytes) return fail(TTC_ERR_WORKSPACE, "workspace too small");
   SweepArgs a;
@@ -260,6 +274,8 @@ ttc_status run_inner(const ttc_tt* x, const ttc_tt* y, double* d_out, Arena& ws,
   a.tcap = sz.tcap;
   a.t_global = tg;
   a.t_stride = sz.tcap;
+  a.i_global = ig;
+  a.i_stride = 2L * sz.max_rp;
   TTC_HIP(launch_sweep(x->dtype, a, 2, sz.lds, s));
   TTC_HIP(launch_meet(x->dtype, W, V, (int)rp, d_out, s));
   return TTC_OK;
@@ -602,6 +618,7 @@ ttc_status tt_contract_inner_bwd_query(const ttc_tt* x, const ttc_tt* y, int32_t
   a.take((size_t)ns * sz.max_rp * cs);
   a.take((size_t)ns * c * sz.max_rp * cs);
   if (sz.t_global) a.take((size_t)std::max(ns, 2) * sz.t_block_bytes);
+  if (sz.i_global) a.take((size_t)std::max(ns, 2) * sz.i_block_bytes);
   *ws_bytes = a.off;
   return TTC_OK;
 }
@@ -637,6 +654,8 @@ ttc_status tt_contract_inner_bwd(const ttc_tt* x, const ttc_tt* y, const double*
   g.segV = a.take((size_t)ns * c * sz.max_rp * cs);
   g.t_global = sz.t_global ? a.take((size_t)std::max(ns, 2) * sz.t_block_bytes) : nullptr;
   g.t_stride = sz.tcap;
+  g.i_global = sz.i_global ? a.take((size_t)std::max(ns, 2) * sz.i_block_bytes) : nullptr;
+  g.i_stride = 2L * sz.max_rp;
   g.gz = d_gz;
   g.max_rp = sz.max_rp;
   g.tcap = sz.tcap;

@@ -29,6 +29,8 @@ struct SweepArgs {
   int tcap;        // capacity of the per-mode intermediate (elements)
   void* t_global;  // intermediate in global memory (null: in LDS)
   long t_stride;   // elements per block in t_global
+  void* i_global;  // the two interface buffers in global memory (null: in LDS)
+  long i_stride;   // elements per block in i_global (2 * max_rp)
 };
 
 // Left/right checkpoints for the inner-product gradient (phase A) and the
@@ -47,6 +49,8 @@ struct GradArgs {
   int tcap;
   void* t_global;
   long t_stride;
+  void* i_global;
+  long i_stride;
 };
 
 // Natural-order lift of a junction matrix K (see tt_contract_modes).

@@ -1,0 +1,44 @@
+// Internal interface of the TT-layer kernels (GEMM, permutations, loss).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "ttc_internal.h"
+
+namespace ttc {
+
+// C (M x N, row-major, ldc) = alpha * A . B with
+//   A(m, k) = a_kc ? A[m * lda + k] : A[k * lda + m]
+//   B(k, n) = b_kc ? B[n * ldb + k] : B[k * ldb + n]
+// splits > 1: K is cut into `splits` ranges whose partial products go to
+// slab (splits x M x N) and are summed in order by a second kernel.
+struct GemmArgs {
+  int M, N, K;
+  long lda, ldb, ldc;
+  const float* A;
+  const float* B;
+  float* C;
+  float alpha;
+  int splits;
+  float* slab;
+  bool vec_a, vec_b;  // 16-byte vector loads allowed
+};
+
+struct PermArgs {
+  int dir;            // 0: pair-mode order -> matrix, 1: matrix -> pair-mode order
+  int d;
+  int I[TTC_MAX_ORDER], J[TTC_MAX_ORDER];
+  long pstride[TTC_MAX_ORDER];
+  long cols;          // prod J
+  long total;
+  const float* src;
+  float* dst;
+};
+
+hipError_t launch_gemm(bool a_kc, bool b_kc, bool bf16, const GemmArgs& g, hipStream_t s);
+int gemm_bk(bool bf16);
+hipError_t launch_permute(const PermArgs& p, hipStream_t s);
+int mse_blocks(long n);
+hipError_t launch_mse(const float* y, const float* t, long n, float* dy, double* partials, double* out,
+                      hipStream_t s);
+
+}  // namespace ttc

@@ -1,0 +1,112 @@
+"""GPU parity of the batched persistent sweep (inner product + junction of
+the contraction over the last two positions, per pair) against the FP64
+oracle, through the C ABI: a small uneven batch checked in full, and the
+4096-pair batch checked on sampled pairs (FP32 and BF16 inputs), against the
+per-pair launch loop, and for run-to-run determinism."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import tt_oracle as O
+from ttgen import configs as C
+
+from helpers import TOL, rel_fro, scalar_err, to_gpu, to_np, tt_norm
+
+pytestmark = pytest.mark.gpu
+
+
+def _oracle_pair(x, y):
+    N = len(x)
+    z = O.inner_lr(x, y)
+    K = O.sweep_rl(x, y, downto=N - 2)[N - 2]
+    return z, K
+
+
+def _check_pairs(plan, inner, junc, cores64, idx, tol):
+    worst = 0.0
+    for p in idx:
+        x, y = cores64[p]
+        z, K = _oracle_pair(x, y)
+        e = scalar_err(float(inner[p]), z, tt_norm(x), tt_norm(y))
+        ek = rel_fro(to_np(plan.junction(junc, p)), K)
+        worst = max(worst, e, ek)
+        assert e <= tol, (p, e)
+        assert ek <= tol, (p, ek)
+    return worst
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_batch_small_uneven(ttc, dtype):
+    shapes = C.batch_pair_shapes(C.SEED_BATCH, 40)
+    # plus degenerate shapes: order 3 with rank-1 bonds, order 12 small ranks
+    shapes.append((C.TTShape([4, 4, 4], [1, 1, 1, 1]), C.TTShape([4, 4, 4], [1, 1, 1, 1])))
+    shapes.append((C.TTShape([5] * 12, [1] + [3] * 11 + [1]), C.TTShape([5] * 12, [1] + [2] * 11 + [1])))
+    cores64, gpu = [], []
+    for p, (sx, sy) in enumerate(shapes):
+        x = C.gen_tt_np(C.SEED_BATCH, 1 + 2 * p, sx)
+        y = C.gen_tt_np(C.SEED_BATCH, 2 + 2 * p, sy)
+        xg, xs = to_gpu(x, dtype)
+        yg, ys = to_gpu(y, dtype)
+        cores64.append((x, y) if dtype == "bf16" else (xs, ys))
+        gpu.append((xg, yg))
+    plan = ttc.BatchPlan(gpu)
+    inner, junc = plan.run()
+    inner = to_np(inner)
+    _check_pairs(plan, inner, junc, cores64, range(len(shapes)), TOL[dtype])
+    # the per-pair launch loop gives the same results
+    inner2, junc2 = plan.run(plain=True)
+    assert np.max(np.abs(to_np(inner2) - inner) / np.maximum(np.abs(inner), 1e-30)) <= 1e-5
+    # determinism of the batched launch (graph replay)
+    inner3, junc3 = plan.outputs()
+    plan.run(inner3, junc3)
+    plan.run(inner3, junc3)
+    assert np.array_equal(to_np(inner3), inner)
+
+
+def test_batch_integer_cores_exact(ttc):
+    pairs, want = [], []
+    for p in range(12):
+        r = 2 + p % 5
+        s = C.TTShape([3, 5, 4, 2], [1, r, 3, r + 1, 1])
+        x = C.gen_int_tt_np(500 + p, 1, s)
+        y = C.gen_int_tt_np(500 + p, 2, s)
+        xg, _ = to_gpu(x, "bf16")
+        yg, _ = to_gpu(y, "bf16")
+        pairs.append((xg, yg))
+        want.append(_oracle_pair(x, y))
+    plan = ttc.BatchPlan(pairs)
+    inner, junc = plan.run()
+    for p, (z, K) in enumerate(want):
+        assert float(inner[p]) == z
+        assert np.array_equal(to_np(plan.junction(junc, p)), K)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_batch4096_sampled(ttc, dtype):
+    import torch
+    shapes = C.batch_pair_shapes(C.SEED_BATCH, 4096)
+    td = torch.float32 if dtype == "f32" else torch.bfloat16
+    pairs = C.gen_batch_torch(C.SEED_BATCH, shapes, "cuda", td)
+    plan = ttc.BatchPlan(pairs)
+    inner, junc = plan.run()
+    inner_np = to_np(inner)
+    rs = np.random.RandomState(1 if dtype == "f32" else 2)
+    # the heaviest pairs and a random sample
+    cost = [sum(sx.ranks[k] * sx.modes[k] * sx.ranks[k + 1] * (sy.ranks[k] + sy.ranks[k + 1])
+                for k in range(sx.order)) for sx, sy in shapes]
+    idx = list(np.argsort(cost)[-3:]) + list(rs.choice(4096, 12, replace=False))
+    cores64 = {}
+    for p in idx:
+        x, y = pairs[p]
+        if dtype == "f32":
+            cores64[p] = ([to_np(t) for t in x], [to_np(t) for t in y])
+        else:  # total error against the unrounded FP64 values
+            cores64[p] = (C.gen_tt_np(C.SEED_BATCH, 1 + 2 * p, shapes[p][0]),
+                          C.gen_tt_np(C.SEED_BATCH, 2 + 2 * p, shapes[p][1]))
+    _check_pairs(plan, inner_np, junc, cores64, idx, TOL[dtype])
+    assert np.all(np.isfinite(inner_np))
+    inner2, junc2 = plan.outputs()
+    plan.run(inner2, junc2)
+    assert np.array_equal(to_np(inner2), inner_np)
+    assert torch.equal(junc2, junc)

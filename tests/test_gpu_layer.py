@@ -1,0 +1,123 @@
+"""GPU parity of the TT layer (TT-matrix x dense batch, MSE loss, backward)
+against the FP64 oracle's dense route, through the C ABI."""
+import numpy as np
+import pytest
+
+from oracle import tt_oracle as O
+from ttgen import configs as C
+
+from helpers import TOL, max_core_rel, rel_fro, to_gpu, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+def _batch(seed, obj, rows, cols):
+    return C.gen_matrix_np(seed, obj, rows, cols)
+
+
+def _upload(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to(torch.float32).cuda()
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_layer_fd_instance(ttc, prec):
+    """Order 3, I = J = 4, ranks (1,4,4,1), batch 8: forward, loss and every
+    gradient against the oracle's FP64 dense route (which itself is pinned by
+    finite differences)."""
+    s = C.layer_fd_shape()
+    w = C.gen_tt_np(C.SEED_LAYER, 11, s)
+    X = _batch(C.SEED_LAYER, 12, 8, 64)
+    T = _batch(C.SEED_LAYER, 13, 8, 64)
+    wg, ws = to_gpu(w, "f32")
+    Xg, Tg = _upload(X), _upload(T)
+    Xs, Ts = to_np(Xg), to_np(Tg)
+    ref = O.layer_forward_backward(ws, Xs, Ts) if prec == "f32" else O.layer_forward_backward(w, X, T)
+    tol = TOL[prec]
+    Y = ttc.ttm_apply_dense(wg, Xg, prec=prec)
+    assert rel_fro(to_np(Y), ref["Y"]) <= tol
+    L, dY = ttc.ttc_mse_loss(Y, Tg)
+    assert abs(L.item() - ref["L"]) <= tol * ref["L"]
+    assert rel_fro(to_np(dY), ref["dY"]) <= tol
+    dX, dG = ttc.ttm_apply_dense_bwd(wg, Xg, dY, prec=prec)
+    assert rel_fro(to_np(dX), ref["dX"]) <= tol
+    assert max_core_rel([to_np(g) for g in dG], ref["dG"]) <= tol
+
+
+def test_layer_autograd_matches_oracle(ttc):
+    import torch
+    s = C.TTShape([4, 2, 3], [1, 3, 5, 1], [3, 4, 2])   # rectangular: 24 x 24
+    w = C.gen_tt_np(C.SEED_LAYER, 21, s)
+    X = _batch(C.SEED_LAYER, 22, 37, 24)                   # ragged batch
+    T = _batch(C.SEED_LAYER, 23, 37, 24)
+    wg, ws = to_gpu(w, "f32")
+    Xg, Tg = _upload(X), _upload(T)
+    ref = O.layer_forward_backward(ws, to_np(Xg), to_np(Tg))
+    cores = [c.clone().requires_grad_(True) for c in wg]
+    xv = Xg.clone().requires_grad_(True)
+    Y = ttc.tt_linear(xv, cores)
+    L, dY = ttc.ttc_mse_loss(Y.detach(), Tg)
+    Y.backward(dY)
+    assert rel_fro(to_np(xv.grad), ref["dX"]) <= TOL["f32"]
+    assert max_core_rel([to_np(c.grad) for c in cores], ref["dG"]) <= TOL["f32"]
+
+
+def test_layer4_full_size(ttc):
+    """Order-4 TT-matrix 4096 -> 4096 (modes 8, ranks 32), batch 8192 x 4096:
+    forward rows and backward rows sampled against the oracle; the loss
+    against its definition on the GPU's Y; the core gradients by the Euler
+    identity <dL/dG_k, G_k> = <dL/dY, Y> (Y is linear in each core), and at a
+    reduced batch of 256 rows against the oracle in full."""
+    import torch
+    s = C.layer4_shape()
+    w = C.gen_tt_np(C.SEED_LAYER, 1, s)
+    wg, ws = to_gpu(w, "f32")
+    B, D = 8192, 4096
+    Xg = C.gen_matrix_torch(C.SEED_LAYER, 2, B, D, "cuda", torch.float32)
+    Tg = C.gen_matrix_torch(C.SEED_LAYER, 3, B, D, "cuda", torch.float32)
+    Y = ttc.ttm_apply_dense(wg, Xg)
+    Wd = O.mpo_full(ws)
+    rows = np.random.RandomState(0).choice(B, 48, replace=False)
+    Xr = to_np(Xg[rows])
+    assert rel_fro(to_np(Y[rows]), Xr @ Wd.T) <= TOL["f32"]
+    L, dY = ttc.ttc_mse_loss(Y, Tg)
+    Yn = to_np(Y)
+    Tn = to_np(Tg)
+    Lref = float(np.mean((Yn - Tn) ** 2))
+    assert abs(L.item() - Lref) <= 1e-10 * Lref
+    dX, dG = ttc.ttm_apply_dense_bwd(wg, Xg, dY)
+    dYr = to_np(dY[rows])
+    assert rel_fro(to_np(dX[rows]), dYr @ Wd) <= TOL["f32"]
+    euler = float(np.sum(to_np(dY) * Yn))
+    for k in range(4):
+        got = float(np.sum(to_np(dG[k]) * ws[k]))
+        assert abs(got - euler) <= 1e-4 * abs(euler)
+    # reduced batch, full oracle
+    Xs, Ts = Xg[:256].contiguous(), Tg[:256].contiguous()
+    Ys = ttc.ttm_apply_dense(wg, Xs)
+    _, dYs = ttc.ttc_mse_loss(Ys, Ts)
+    dXs, dGs = ttc.ttm_apply_dense_bwd(wg, Xs, dYs)
+    ref = O.layer_forward_backward(ws, to_np(Xs), to_np(Ts))
+    assert rel_fro(to_np(dXs), ref["dX"]) <= TOL["f32"]
+    assert max_core_rel([to_np(g) for g in dGs], ref["dG"]) <= TOL["f32"]
+
+
+def test_layer4_bf16_forward(ttc):
+    import torch
+    s = C.layer4_shape()
+    w = C.gen_tt_np(C.SEED_LAYER, 1, s)
+    wg, ws = to_gpu(w, "f32")
+    Xg = C.gen_matrix_torch(C.SEED_LAYER, 2, 512, 4096, "cuda", torch.float32)
+    Y = ttc.ttm_apply_dense(wg, Xg, prec="bf16")
+    ref = to_np(Xg) @ O.mpo_full(w).T
+    assert rel_fro(to_np(Y), ref) <= TOL["bf16"]
+
+
+def test_mse_loss_odd_size(ttc):
+    import torch
+    y = torch.randn(1001, device="cuda")
+    t = torch.randn(1001, device="cuda")
+    L, dy = ttc.ttc_mse_loss(y, t)
+    yn, tn = to_np(y), to_np(t)
+    assert abs(L.item() - np.mean((yn - tn) ** 2)) <= 1e-12 * np.mean((yn - tn) ** 2)
+    assert rel_fro(to_np(dy), 2 * (yn - tn) / 1001) <= 1e-6

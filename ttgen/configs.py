@@ -172,3 +172,70 @@ def cast_np(v64: np.ndarray, dtype: str) -> np.ndarray:
     if dtype == "bf16":
         return rng.round_to_bf16(v64)
     raise ValueError(dtype)
+
+
+def gen_many_torch(specs, device, dtype, chunk_elems=1 << 27):
+    """Fill many cores in one flat device buffer.  specs: list of
+    (seed, obj, core_id, shape, sigma2).  Element e of a core uses the same
+    counters (2e, 2e + 1) under the same key as gen_tt_np / gen_tt_torch, so
+    the values agree with theirs up to the last bit of Box-Muller.  Returns
+    one tensor view per spec (contiguous, in spec order)."""
+    import torch
+    sizes = [int(np.prod(s[3])) for s in specs]
+    total = int(sum(sizes))
+    flat = torch.empty(max(total, 1), dtype=dtype, device=device)
+    views = []
+    off = 0
+    i = 0
+    while i < len(specs):
+        j, acc = i, 0
+        while j < len(specs) and (acc == 0 or acc + sizes[j] <= chunk_elems):
+            acc += sizes[j]
+            j += 1
+        keys = torch.tensor([rng._s64(rng.derive_key(s[0], s[1], s[2])) for s in specs[i:j]],
+                            dtype=torch.int64, device=device)
+        scl = torch.tensor([math.sqrt(s[4]) for s in specs[i:j]], dtype=torch.float64, device=device)
+        cnt = torch.tensor(sizes[i:j], dtype=torch.int64, device=device)
+        starts = torch.cumsum(cnt, 0) - cnt
+        kk = torch.repeat_interleave(keys, cnt)
+        ss = torch.repeat_interleave(scl, cnt)
+        e = torch.arange(acc, dtype=torch.int64, device=device) - torch.repeat_interleave(starts, cnt)
+        z0 = rng._mix64_t((2 * e + 1) * rng._s64(rng.GAMMA) + kk)
+        z1 = rng._mix64_t((2 * e + 2) * rng._s64(rng.GAMMA) + kk)
+        del e
+        u0 = rng._lsr(z0, 11).to(torch.float64) * (2.0 ** -53)
+        u1 = rng._lsr(z1, 11).to(torch.float64) * (2.0 ** -53)
+        del z0, z1
+        v = torch.sqrt(-2.0 * torch.log(1.0 - u0)) * torch.cos(2.0 * np.pi * u1) * ss
+        flat[off:off + acc] = cast_t(v, dtype)
+        del u0, u1, v, kk, ss
+        off += acc
+        i = j
+    off = 0
+    for s, n in zip(specs, sizes):
+        views.append(flat[off:off + n].view(*s[3]))
+        off += n
+    return views
+
+
+def batch_specs(seed: int, shapes):
+    """Generator specs of the uneven batch: X of pair p is object 1 + 2p,
+    Y is object 2 + 2p; core k of each has sigma2 = 1 / max(R_k, R_{k+1})."""
+    specs = []
+    for p, (sx, sy) in enumerate(shapes):
+        for obj, sh in ((1 + 2 * p, sx), (2 + 2 * p, sy)):
+            for k in range(sh.order):
+                specs.append((seed, obj, k, sh.core_shape(k), sigma2_of(sh, k)))
+    return specs
+
+
+def gen_batch_torch(seed: int, shapes, device, dtype):
+    views = gen_many_torch(batch_specs(seed, shapes), device, dtype)
+    pairs, i = [], 0
+    for sx, sy in shapes:
+        x = views[i:i + sx.order]
+        i += sx.order
+        y = views[i:i + sy.order]
+        i += sy.order
+        pairs.append((x, y))
+    return pairs
