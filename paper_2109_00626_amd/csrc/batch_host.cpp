@@ -59,8 +59,9 @@ struct ttc_plan {
   std::vector<double> cost;
   double flops = 0, bytes = 0;
   long max_rp = 1, max_t = 1;
-  // device memory (one allocation)
+  // device memory (one allocation for the tables, one for the level buffers)
   void* dmem = nullptr;
+  void* dmem_levels = nullptr;
   PairDev* d_pairs = nullptr;
   int* d_ipool = nullptr;
   void** d_ppool = nullptr;
@@ -75,6 +76,18 @@ struct ttc_plan {
   LaunchCfg cfg;
   int grid = 0;
   int lds_elems = 0;
+  // level-by-level execution
+  int mode = 0;                // 0: persistent kernel, 1: one launch per level
+  int levels = 0;              // max order - 1
+  std::vector<int> lvl_off;    // item offsets per level (levels + 1 entries; level l at index l-1)
+  int n_meet = 0;
+  LevelItem* d_items = nullptr;
+  LevelItem* d_meet = nullptr;
+  float* d_vbuf = nullptr;
+  long* d_voff = nullptr;
+  long* d_vcap = nullptr;
+  float* d_one = nullptr;
+  size_t lvl_lds = 0, meet_lds = 0;
   // graph
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
@@ -101,6 +114,7 @@ ttc_status check_pair_desc(const ttc_pair& p, int idx, uint32_t ops, ttc_dtype* 
     if (t->ranks[0] != 1 || t->ranks[t->order] != 1) return fail(TTC_ERR_RANK, nm + ": boundary ranks must be 1");
     for (int k = 0; k < t->order; ++k) {
       if (t->modes[k] < 1 || t->ranks[k] < 1) return fail(TTC_ERR_SHAPE, nm + ": bad shape");
+      if (t->ranks[k] > 128) return fail(TTC_ERR_UNSUPPORTED, nm + ": batched ranks are limited to 128");
       if (!t->cores[k]) return fail(TTC_ERR_NULL, nm + ": NULL core pointer");
     }
   }
@@ -177,6 +191,47 @@ BatchArgs make_args(ttc_plan* P, const int* begin, const int* order, double* inn
   return a;
 }
 
+LevelArgs make_level_args(ttc_plan* P, double* inner, float* junc) {
+  LevelArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.pairs = P->d_pairs;
+  a.ipool = P->d_ipool;
+  a.ppool = P->d_ppool;
+  a.ops = P->ops;
+  a.vbuf = P->d_vbuf;
+  a.voff = P->d_voff;
+  a.vcap = P->d_vcap;
+  a.inner = inner;
+  a.junction = junc;
+  a.one = P->d_one;
+  return a;
+}
+
+hipError_t run_levels(ttc_plan* P, double* inner, float* junc, hipStream_t s) {
+  LevelArgs a = make_level_args(P, inner, junc);
+  for (int l = 1; l <= P->levels; ++l) {
+    a.level = l;
+    a.items = P->d_items + P->lvl_off[l - 1];
+    const int n = P->lvl_off[l] - P->lvl_off[l - 1];
+    hipError_t e = launch_level(P->dt, a, n, P->lvl_lds, s);
+    if (e != hipSuccess) return e;
+  }
+  if (P->ops & TTC_OP_INNER) {
+    a.items = P->d_meet;
+    return launch_meet_level(P->dt, a, P->n_meet, P->meet_lds, s);
+  }
+  return hipSuccess;
+}
+
+hipError_t run_persistent(ttc_plan* P, double* inner, float* junc, hipStream_t s) {
+  BatchArgs a = make_args(P, P->d_begin, P->d_order, inner, junc, P->lds_elems, P->grid);
+  return launch_batch(P->dt, a, P->grid, P->cfg.threads, s);
+}
+
+hipError_t run_mode(ttc_plan* P, double* inner, float* junc, hipStream_t s) {
+  return P->mode == 1 ? run_levels(P, inner, junc, s) : run_persistent(P, inner, junc, s);
+}
+
 ttc_status upload_assignment(ttc_plan* P, const LaunchCfg& c, int* grid_out, int* lds_out) {
   const int grid = std::min(P->cus * c.per_cu, std::max(P->n, 1));
   std::vector<int> begin, order;
@@ -235,7 +290,9 @@ void cache_store(const std::string& key, const LaunchCfg& c) {
 ttc_status autotune(ttc_plan* P) {
   const std::string key = cache_key(P);
   LaunchCfg best;
-  if (cache_lookup(key, &best)) {
+  if (!std::getenv("TTC_BATCH_MODE") && cache_lookup(key, &best)) {
+    P->mode = best.threads < 0 ? 1 : 0;
+    if (best.threads < 0) best.threads = 256;
     P->cfg = best;
     return upload_assignment(P, best, &P->grid, &P->lds_elems);
   }
@@ -264,12 +321,28 @@ ttc_status autotune(ttc_plan* P) {
       best = c;
     }
   }
+  // the level-by-level schedule
+  P->mode = 1;
+  TTC_HIP(run_levels(P, d_inner, d_junc, 0));
+  TTC_HIP(hipEventRecord(e0, 0));
+  for (int r = 0; r < 2; ++r) TTC_HIP(run_levels(P, d_inner, d_junc, 0));
+  TTC_HIP(hipEventRecord(e1, 0));
+  TTC_HIP(hipEventSynchronize(e1));
+  float lv_ms = 0;
+  TTC_HIP(hipEventElapsedTime(&lv_ms, e0, e1));
+  P->mode = lv_ms < best_ms ? 1 : 0;
+  if (const char* fm = std::getenv("TTC_BATCH_MODE")) {  // forced schedule (testing)
+    if (std::strcmp(fm, "levels") == 0) P->mode = 1;
+    if (std::strcmp(fm, "persistent") == 0) P->mode = 0;
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   (void)hipFree(d_inner);
   (void)hipFree(d_junc);
   P->cfg = best;
+  if (P->mode == 1) best.threads = -1;  // cache entry marks the level schedule
   cache_store(key, best);
+  best.threads = P->cfg.threads;
   return upload_assignment(P, best, &P->grid, &P->lds_elems);
 }
 
@@ -278,6 +351,8 @@ void release(ttc_plan* P) {
   if (P->graph) (void)hipGraphDestroy(P->graph);
   if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
   if (P->dmem) (void)hipFree(P->dmem);
+  if (P->dmem_levels) (void)hipFree(P->dmem_levels);
+  P->dmem_levels = nullptr;
   P->exec = nullptr;
   P->graph = nullptr;
   P->cap_stream = nullptr;
@@ -343,8 +418,7 @@ ttc_status tt_batch_plan_create(const ttc_pair* pairs, int32_t n, uint32_t ops, 
     P->flops += fl;
     P->bytes += by;
     P->cost[i] = fl_exec + 16.0 * by;  // FLOPs plus memory time at ~16 FLOP/byte
-    for (int b = 1; b <= N; ++b) P->max_rp = std::max<long>(P->max_rp, (long)h.rx[b] * h.ry[b]);
-    for (int k = 1; k < N; ++k) P->max_t = std::max<long>(P->max_t, (long)h.rx[k] * h.ry[k + 1]);
+    for (int b = 1; b <= N; ++b) P->max_rp = std::max<long>(P->max_rp, (long)h.rx[b] * ((h.ry[b] & 1) ? h.ry[b] : h.ry[b] + 1));
   }
   hipError_t e = hipGetDevice(&P->device);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&P->cus, hipDeviceAttributeMultiprocessorCount, P->device);
@@ -408,6 +482,77 @@ ttc_status tt_batch_plan_create(const ttc_pair* pairs, int32_t n, uint32_t ops, 
     hipError_t ee = batch_set_lds(kLdsBytes);
     if (ee != hipSuccess) st = fail(TTC_ERR_HIP, std::string("kernel attribute: ") + hipGetErrorString(ee));
   }
+  // level-by-level tables: items (pair, 16-row tile) of every level, heavy first
+  if (st == TTC_OK) {
+    int maxN = 0;
+    for (const PairHost& h : P->pairs) maxN = std::max(maxN, h.order);
+    P->levels = maxN - 1;
+    std::vector<LevelItem> items;
+    P->lvl_off.assign(1, 0);
+    for (int l = 1; l <= P->levels; ++l) {
+      std::vector<std::pair<double, LevelItem>> lv;
+      for (int q = 0; q < n; ++q) {
+        const PairHost& h = P->pairs[q];
+        const int k = h.order - l;
+        if (k < 1) continue;
+        const int RT = (h.rx[k] + 15) / 16;
+        const double c = (double)h.modes[k] * ((h.ry[k + 1] + 15) / 16) *
+                         ((h.rx[k + 1] + 15) / 16 + (h.ry[k] + 15) / 16);
+        for (int rt = 0; rt < RT; ++rt) lv.push_back({c, LevelItem{q, rt}});
+      }
+      std::stable_sort(lv.begin(), lv.end(), [](const std::pair<double, LevelItem>& a,
+                                                const std::pair<double, LevelItem>& b) { return a.first > b.first; });
+      for (auto& e : lv) items.push_back(e.second);
+      P->lvl_off.push_back((int)items.size());
+    }
+    std::vector<LevelItem> meet;
+    for (int q = 0; q < n; ++q) meet.push_back(LevelItem{q, 0});
+    P->n_meet = n;
+    std::vector<long> voff(n), vcap(n);
+    long vtot = 0;
+    int maxP = 1, maxW1 = 1;
+    for (int q = 0; q < n; ++q) {
+      const PairHost& h = P->pairs[q];
+      long cap = 1;
+      for (int b = 1; b < h.order; ++b) cap = std::max(cap, (long)h.rx[b] * h.ry[b]);
+      for (int b = 1; b <= h.order; ++b) maxP = std::max(maxP, h.ry[b]);
+      maxW1 = std::max(maxW1, h.rx[1] * h.ry[1]);
+      cap = (cap + 3) & ~3L;
+      voff[q] = vtot;
+      vcap[q] = cap;
+      vtot += 2 * cap;
+    }
+    P->lvl_lds = (size_t)4 * 16 * maxP * sizeof(float);
+    P->meet_lds = (size_t)maxW1 * sizeof(float);
+    void* lm = nullptr;
+    const size_t b_items = al(sizeof(LevelItem) * std::max<size_t>(items.size(), 1));
+    const size_t b_meet = al(sizeof(LevelItem) * n);
+    const size_t b_off = al(sizeof(long) * n);
+    const size_t b_v = al(sizeof(float) * vtot);
+    hipError_t ee = hipMalloc(&lm, b_items + b_meet + 2 * b_off + b_v + 256);
+    if (ee != hipSuccess) {
+      st = fail(TTC_ERR_HIP, std::string("plan allocation: ") + hipGetErrorString(ee));
+    } else {
+      P->dmem_levels = lm;
+      char* c = (char*)lm;
+      P->d_items = (LevelItem*)c;
+      P->d_meet = (LevelItem*)(c + b_items);
+      P->d_voff = (long*)(c + b_items + b_meet);
+      P->d_vcap = (long*)(c + b_items + b_meet + b_off);
+      P->d_vbuf = (float*)(c + b_items + b_meet + 2 * b_off);
+      P->d_one = (float*)(c + b_items + b_meet + 2 * b_off + b_v);
+      const float one = 1.f;
+      cp(P->d_one, &one, sizeof(float));
+      cp(P->d_items, items.data(), sizeof(LevelItem) * items.size());
+      cp(P->d_meet, meet.data(), sizeof(LevelItem) * n);
+      cp(P->d_voff, voff.data(), sizeof(long) * n);
+      cp(P->d_vcap, vcap.data(), sizeof(long) * n);
+    }
+    if (st == TTC_OK) {
+      ee = level_set_lds((int)P->lvl_lds, (int)P->meet_lds);
+      if (ee != hipSuccess) st = fail(TTC_ERR_HIP, std::string("kernel attribute: ") + hipGetErrorString(ee));
+    }
+  }
   if (st == TTC_OK) st = autotune(P);
   if (st == TTC_OK) {
     hipError_t ee = hipDeviceSynchronize();
@@ -435,9 +580,8 @@ ttc_status tt_batch_run(ttc_plan* P, double* d_inner, float* d_junction, void* s
   if ((P->ops & TTC_OP_INNER) && !d_inner) return fail(TTC_ERR_NULL, "d_inner is NULL");
   if ((P->ops & TTC_OP_SUFFIX2) && !d_junction) return fail(TTC_ERR_NULL, "d_junction is NULL");
   hipStream_t s = (hipStream_t)stream;
-  BatchArgs a = make_args(P, P->d_begin, P->d_order, d_inner, d_junction, P->lds_elems, P->grid);
   if (!s) {
-    TTC_HIP(launch_batch(P->dt, a, P->grid, P->cfg.threads, s));
+    TTC_HIP(run_mode(P, d_inner, d_junction, s));
     return TTC_OK;
   }
   if (!P->exec || P->g_inner != d_inner || P->g_junc != d_junction) {
@@ -451,7 +595,7 @@ ttc_status tt_batch_run(ttc_plan* P, double* d_inner, float* d_junction, void* s
     }
     if (!P->cap_stream) TTC_HIP(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking));
     TTC_HIP(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal));
-    hipError_t le = launch_batch(P->dt, a, P->grid, P->cfg.threads, P->cap_stream);
+    hipError_t le = run_mode(P, d_inner, d_junction, P->cap_stream);
     hipGraph_t g = nullptr;
     hipError_t ce = hipStreamEndCapture(P->cap_stream, &g);
     if (le != hipSuccess) return fail(TTC_ERR_HIP, std::string("capture launch: ") + hipGetErrorString(le));

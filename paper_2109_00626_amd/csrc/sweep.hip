@@ -11,6 +11,7 @@
 //   S_i = G_x^(k)[:, i, :] . V_{k+1};  V_k += sum_i S_i . G_y^(k)[:, i, :]^T
 // Interfaces and the per-mode intermediate live in LDS when they fit,
 // otherwise in a per-block slice of the caller's workspace.
+#include "sweep_steps.hpp"
 #include "ttc_device.hpp"
 #include "ttc_internal.h"
 
@@ -98,6 +99,31 @@ __device__ Tc* run_sweep(const TTDev& x, const TTDev& y, int dir, int stop, Tc* 
   return cur;
 }
 
+// Chained-MFMA sweep (ranks <= 128); interfaces use the odd-pitch layout.
+template <typename Tin, typename Tc>
+__device__ Tc* run_sweep_chain(const TTDev& x, const TTDev& y, int dir, int stop, Tc* bufA, Tc* bufB) {
+  if (threadIdx.x == 0) bufA[0] = (Tc)1;
+  __syncthreads();
+  Tc* cur = bufA;
+  Tc* nxt = bufB;
+  if (dir == 0) {
+    for (int k = 0; k < stop; ++k) {
+      lr_step_chain<Tin, Tc>(x, y, k, cur, iface_pitch(y.ranks[k]), nxt, iface_pitch(y.ranks[k + 1]));
+      Tc* t = cur;
+      cur = nxt;
+      nxt = t;
+    }
+  } else {
+    for (int k = x.order - 1; k >= stop; --k) {
+      rl_step_chain<Tin, Tc>(x, y, k, cur, iface_pitch(y.ranks[k + 1]), nxt, iface_pitch(y.ranks[k]));
+      Tc* t = cur;
+      cur = nxt;
+      nxt = t;
+    }
+  }
+  return cur;
+}
+
 template <typename Tin, typename Tc>
 __global__ __launch_bounds__(256) void sweep_kernel(SweepArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -106,11 +132,19 @@ __global__ __launch_bounds__(256) void sweep_kernel(SweepArgs a) {
   if (dir < 0) return;
   Tc* bufA = a.i_global ? reinterpret_cast<Tc*>(a.i_global) + b * a.i_stride : reinterpret_cast<Tc*>(smem);
   Tc* bufB = bufA + a.max_rp;
+  const int stop = a.stop[b];
+  const int R = a.x.ranks[stop], P = a.y.ranks[stop];
+  Tc* out = reinterpret_cast<Tc*>(a.out[b]);
+  if (a.chain) {
+    Tc* res = run_sweep_chain<Tin, Tc>(a.x, a.y, dir, stop, bufA, bufB);
+    const int ld = iface_pitch(P);
+    for (int e = threadIdx.x; e < R * P; e += blockDim.x) out[e] = res[(e / P) * ld + (e % P)];
+    return;
+  }
   Tc* lds_free = a.i_global ? reinterpret_cast<Tc*>(smem) : bufB + a.max_rp;
   Tc* T = a.t_global ? reinterpret_cast<Tc*>(a.t_global) + b * a.t_stride : lds_free;
-  Tc* res = run_sweep<Tin, Tc>(a.x, a.y, dir, a.stop[b], bufA, bufB, T, a.tcap);
-  const int n = a.x.ranks[a.stop[b]] * a.y.ranks[a.stop[b]];
-  wg_copy<Tc>(reinterpret_cast<Tc*>(a.out[b]), res, n);
+  Tc* res = run_sweep<Tin, Tc>(a.x, a.y, dir, stop, bufA, bufB, T, a.tcap);
+  wg_copy<Tc>(out, res, R * P);
 }
 
 // z = sum W .* V, products and sum in FP64 (deterministic tree).

@@ -30,7 +30,31 @@ struct BatchArgs {
   float* junction;
 };
 
+// Level-by-level execution: one launch per step index from the right.
+struct LevelItem {
+  int pair;
+  int rt;      // 16-row tile of V_k
+};
+
+struct LevelArgs {
+  const PairDev* pairs;
+  const int* ipool;
+  const void* const* ppool;
+  const LevelItem* items;  // items of this launch
+  int level;               // step k = N - level of each item's pair
+  unsigned ops;
+  float* vbuf;             // two interface slots per pair
+  const long* voff;        // per pair: offset of its slots in vbuf
+  const long* vcap;        // per pair: elements per slot
+  double* inner;
+  float* junction;
+  const float* one;        // V_N = [1]
+};
+
 hipError_t batch_set_lds(int bytes);
+hipError_t level_set_lds(int level_bytes, int meet_bytes);
+hipError_t launch_level(ttc_dtype dt, const LevelArgs& a, int nitems, size_t lds, hipStream_t s);
+hipError_t launch_meet_level(ttc_dtype dt, const LevelArgs& a, int npairs, size_t lds, hipStream_t s);
 hipError_t launch_batch(ttc_dtype dt, const BatchArgs& a, int grid, int threads, hipStream_t s);
 
 }  // namespace ttc

@@ -117,17 +117,26 @@ struct SweepSizing {
   int tcap = 1;
   bool t_global = false;
   bool i_global = false;
+  bool chain = false;
   size_t lds = 0;
   size_t t_block_bytes = 0;
   size_t i_block_bytes = 0;
 };
 
 // Interfaces and the per-mode intermediate go to LDS when they fit; what
-// does not fit goes to a per-block slice of the workspace.
-ttc_status size_sweep(const ttc_tt* x, const ttc_tt* y, int k0, int k1, SweepSizing* out) {
+// does not fit goes to a per-block slice of the workspace.  With every rank
+// <= 128 the chained-MFMA steps are used: no intermediate buffer, and
+// interfaces stored with an odd row pitch.
+int iface_pitch_h(int P) { return (P & 1) ? P : P + 1; }
+
+ttc_status size_sweep(const ttc_tt* x, const ttc_tt* y, int k0, int k1, SweepSizing* out, bool allow_chain = true) {
   const size_t cs = comp_size(x->dtype);
   long max_rp = 1, max_t = 1, max_I = 1;
-  for (int b = k0; b <= k1; ++b) max_rp = std::max<long>(max_rp, (long)x->ranks[b] * y->ranks[b]);
+  int max_rank = 1;
+  for (int b = 0; b <= x->order; ++b) max_rank = std::max(max_rank, std::max(x->ranks[b], y->ranks[b]));
+  const bool chain = allow_chain && max_rank <= 128;
+  for (int b = k0; b <= k1; ++b)
+    max_rp = std::max<long>(max_rp, (long)x->ranks[b] * (chain ? iface_pitch_h(y->ranks[b]) : y->ranks[b]));
   for (int k = k0; k < k1; ++k) {
     max_t = std::max<long>(max_t, (long)x->ranks[k] * y->ranks[k + 1]);
     max_I = std::max<long>(max_I, x->modes[k]);
@@ -135,6 +144,7 @@ ttc_status size_sweep(const ttc_tt* x, const ttc_tt* y, int k0, int k1, SweepSiz
   const long budget = lds_limit_bytes() / (long)cs;
   SweepSizing s;
   s.max_rp = (int)max_rp;
+  s.chain = chain;
   long lds_elems = 0;
   if (2 * max_rp <= budget) {
     lds_elems = 2 * max_rp;
@@ -142,14 +152,16 @@ ttc_status size_sweep(const ttc_tt* x, const ttc_tt* y, int k0, int k1, SweepSiz
     s.i_global = true;
     s.i_block_bytes = (size_t)(2 * max_rp) * cs;
   }
-  const long left = budget - lds_elems;
-  if (left >= max_t) {
-    s.tcap = (int)std::min(left, max_t * max_I);
-    lds_elems += s.tcap;
-  } else {
-    s.tcap = (int)(max_t * std::min<long>(max_I, 8));
-    s.t_global = true;
-    s.t_block_bytes = (size_t)s.tcap * cs;
+  if (!chain) {
+    const long left = budget - lds_elems;
+    if (left >= max_t) {
+      s.tcap = (int)std::min(left, max_t * max_I);
+      lds_elems += s.tcap;
+    } else {
+      s.tcap = (int)(max_t * std::min<long>(max_I, 8));
+      s.t_global = true;
+      s.t_block_bytes = (size_t)s.tcap * cs;
+    }
   }
   s.lds = (size_t)lds_elems * cs;
   *out = s;
@@ -242,6 +254,7 @@ ttc_status run_junction(const ttc_tt* x, const ttc_tt* y, BlockKind kind, int k,
   a.t_stride = sz.tcap;
   a.i_global = ig;
   a.i_stride = 2L * sz.max_rp;
+  a.chain = sz.chain;
   TTC_HIP(launch_sweep(x->dtype, a, 1, sz.lds, s));
   return TTC_OK;
 }
@@ -276,6 +289,7 @@ ttc_status run_inner(const ttc_tt* x, const ttc_tt* y, double* d_out, Arena& ws,
   a.t_stride = sz.tcap;
   a.i_global = ig;
   a.i_stride = 2L * sz.max_rp;
+  a.chain = sz.chain;
   TTC_HIP(launch_sweep(x->dtype, a, 2, sz.lds, s));
   TTC_HIP(launch_meet(x->dtype, W, V, (int)rp, d_out, s));
   return TTC_OK;
@@ -611,7 +625,7 @@ ttc_status tt_contract_inner_bwd_query(const ttc_tt* x, const ttc_tt* y, int32_t
   const int c = ckpt_stride > 0 ? std::min<int>(ckpt_stride, N) : default_stride(N);
   const int ns = (N + c - 1) / c;
   SweepSizing sz;
-  TTC_TRY(size_sweep(x, y, 0, N, &sz));
+  TTC_TRY(size_sweep(x, y, 0, N, &sz, false));
   const size_t cs = comp_size(x->dtype);
   Arena a(nullptr);
   a.take((size_t)ns * sz.max_rp * cs);
@@ -640,7 +654,7 @@ ttc_status tt_contract_inner_bwd(const ttc_tt* x, const ttc_tt* y, const double*
   const int c = ckpt_stride > 0 ? std::min<int>(ckpt_stride, N) : default_stride(N);
   const int ns = (N + c - 1) / c;
   SweepSizing sz;
-  TTC_TRY(size_sweep(x, y, 0, N, &sz));
+  TTC_TRY(size_sweep(x, y, 0, N, &sz, false));
   const size_t cs = comp_size(x->dtype);
   Arena a(d_ws);
   GradArgs g;

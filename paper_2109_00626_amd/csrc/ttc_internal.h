@@ -31,6 +31,7 @@ struct SweepArgs {
   long t_stride;   // elements per block in t_global
   void* i_global;  // the two interface buffers in global memory (null: in LDS)
   long i_stride;   // elements per block in i_global (2 * max_rp)
+  int chain;       // chained-MFMA steps (ranks <= 128; odd-pitch interfaces)
 };
 
 // Left/right checkpoints for the inner-product gradient (phase A) and the
