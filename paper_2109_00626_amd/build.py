@@ -25,9 +25,18 @@ FLAGS = [
 ]
 
 
+# Per-source extra flags.  The LDS-resident sweep keeps its accumulators in
+# ordinary vector registers (MFMA results in VGPRs rather than accumulation
+# registers), which avoids copies between the two register files when every
+# operand buffer is live.
+EXTRA = {
+    "batched_lds.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+}
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC] + FLAGS + ["-c", src, "-o", obj]
+    cmd = [HIPCC] + FLAGS + EXTRA.get(os.path.basename(src), []) + ["-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{r.stderr}")

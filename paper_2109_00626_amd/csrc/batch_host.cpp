@@ -44,7 +44,8 @@ struct PairHost {
 
 // One launch shape: workgroup size and workgroups per compute unit.
 struct LaunchCfg {
-  int threads = 512;
+  int mode = 2;
+  int threads = 256;
   int per_cu = 1;
 };
 
@@ -77,7 +78,8 @@ struct ttc_plan {
   int grid = 0;
   int lds_elems = 0;
   // level-by-level execution
-  int mode = 0;                // 0: persistent kernel, 1: one launch per level
+  int mode = 0;                // 0: persistent kernel, 1: one launch per level, 2: LDS-resident persistent kernel
+  int buf_elems = 0;           // LDS-resident kernel: floats per interface buffer
   int levels = 0;              // max order - 1
   std::vector<int> lvl_off;    // item offsets per level (levels + 1 entries; level l at index l-1)
   int n_meet = 0;
@@ -116,6 +118,9 @@ ttc_status check_pair_desc(const ttc_pair& p, int idx, uint32_t ops, ttc_dtype* 
       if (t->modes[k] < 1 || t->ranks[k] < 1) return fail(TTC_ERR_SHAPE, nm + ": bad shape");
       if (t->ranks[k] > 128) return fail(TTC_ERR_UNSUPPORTED, nm + ": batched ranks are limited to 128");
       if (!t->cores[k]) return fail(TTC_ERR_NULL, nm + ": NULL core pointer");
+      // core byte offsets are 32-bit in the kernels (row padding included)
+      if (128.0 * t->modes[k] * 128.0 * 4.0 >= 2147483647.0)
+        return fail(TTC_ERR_UNSUPPORTED, nm + ": batched mode sizes are limited to 32767");
     }
   }
   if (p.x.order != p.y.order) return fail(TTC_ERR_SHAPE, "pair " + std::to_string(idx) + ": orders differ");
@@ -137,10 +142,19 @@ double step_flops(const PairHost& p, int k) {
   return std::min(a, b);
 }
 
-// FLOPs the kernel executes on core k (its fixed order).
+// FLOPs the LDS-resident kernel executes on core k: tiles padded to 16, in
+// the order it picks.
+int pad16h(int n) { return (n + 15) & ~15; }
 double step_flops_exec(const PairHost& p, int k) {
-  const double I = p.modes[k], Rp = p.rx[k], Rn = p.rx[k + 1], Pp = p.ry[k], Pn = p.ry[k + 1];
-  return 2 * I * Rp * Pn * (Rn + Pp);
+  const double I = p.modes[k];
+  const double Rp = pad16h(p.rx[k]), Rn = pad16h(p.rx[k + 1]), Pp = pad16h(p.ry[k]), Pn = pad16h(p.ry[k + 1]);
+  return 2 * I * std::min(Rp * Pn * (Rn + Pp), Pp * Rn * (Pn + Rp));
+}
+
+// Floats of one LDS interface buffer of the LDS-resident kernel for an
+// R x P interface, in either layout (rows padded to 16, pitch padded + 4).
+int lds_iface_elems_h(int R, int P) {
+  return std::max(pad16h(P) * (pad16h(R) + 4), pad16h(R) * (pad16h(P) + 4));
 }
 
 // Static longest-processing-time assignment: pairs sorted by cost, each
@@ -187,6 +201,7 @@ BatchArgs make_args(ttc_plan* P, const int* begin, const int* order, double* inn
   a.t_stride = P->max_t;
   a.inner = inner;
   a.junction = junc;
+  a.buf_elems = P->buf_elems;
   (void)grid;
   return a;
 }
@@ -228,8 +243,21 @@ hipError_t run_persistent(ttc_plan* P, double* inner, float* junc, hipStream_t s
   return launch_batch(P->dt, a, P->grid, P->cfg.threads, s);
 }
 
+hipError_t run_lds(ttc_plan* P, double* inner, float* junc, hipStream_t s) {
+  BatchArgs a = make_args(P, P->d_begin, P->d_order, inner, junc, P->lds_elems, P->grid);
+  return launch_batch_lds(P->dt, a, P->grid, P->cfg.threads, s);
+}
+
 hipError_t run_mode(ttc_plan* P, double* inner, float* junc, hipStream_t s) {
-  return P->mode == 1 ? run_levels(P, inner, junc, s) : run_persistent(P, inner, junc, s);
+  if (P->mode == 1) return run_levels(P, inner, junc, s);
+  if (P->mode == 2) return run_lds(P, inner, junc, s);
+  return run_persistent(P, inner, junc, s);
+}
+
+// Largest number of LDS-resident workgroups per CU.
+int lds_kernel_per_cu(const ttc_plan* P) {
+  const int bytes = 2 * P->buf_elems * (int)sizeof(float) + 4 * 1024;
+  return std::max(1, std::min(2, (160 * 1024) / bytes));
 }
 
 ttc_status upload_assignment(ttc_plan* P, const LaunchCfg& c, int* grid_out, int* lds_out) {
@@ -258,11 +286,11 @@ std::string cache_key(const ttc_plan* P) {
   mix(P->ops);
   mix(P->dt);
   std::ostringstream os;
-  os << "gfx950|abi" << TTC_ABI_VERSION << "|" << std::hex << h;
+  os << "gfx950|abi" << TTC_ABI_VERSION << "|s3|" << std::hex << h;
   return os.str();
 }
 
-// Tiny persistent cache: one "key threads per_cu" line per entry.
+// Tiny persistent cache: one "key mode threads per_cu" line per entry.
 std::mutex g_cache_mu;
 bool cache_lookup(const std::string& key, LaunchCfg* c) {
   const char* path = std::getenv("TTC_AUTOTUNE_CACHE");
@@ -270,9 +298,10 @@ bool cache_lookup(const std::string& key, LaunchCfg* c) {
   std::lock_guard<std::mutex> lk(g_cache_mu);
   std::ifstream f(path);
   std::string k;
-  int t, pc;
-  while (f >> k >> t >> pc)
+  int m, t, pc;
+  while (f >> k >> m >> t >> pc)
     if (k == key) {
+      c->mode = m;
       c->threads = t;
       c->per_cu = pc;
       return true;
@@ -284,19 +313,38 @@ void cache_store(const std::string& key, const LaunchCfg& c) {
   if (!path) return;
   std::lock_guard<std::mutex> lk(g_cache_mu);
   std::ofstream f(path, std::ios::app);
-  f << key << " " << c.threads << " " << c.per_cu << "\n";
+  f << key << " " << c.mode << " " << c.threads << " " << c.per_cu << "\n";
 }
 
 ttc_status autotune(ttc_plan* P) {
   const std::string key = cache_key(P);
+  const char* forced = std::getenv("TTC_BATCH_MODE");  // testing: levels | persistent | lds
+  int want = -1;
+  if (forced) {
+    if (std::strcmp(forced, "persistent") == 0) want = 0;
+    if (std::strcmp(forced, "levels") == 0) want = 1;
+    if (std::strcmp(forced, "lds") == 0) want = 2;
+  }
   LaunchCfg best;
-  if (!std::getenv("TTC_BATCH_MODE") && cache_lookup(key, &best)) {
-    P->mode = best.threads < 0 ? 1 : 0;
-    if (best.threads < 0) best.threads = 256;
+  if (cache_lookup(key, &best) && (want < 0 || want == best.mode)) {
+    P->mode = best.mode;
     P->cfg = best;
     return upload_assignment(P, best, &P->grid, &P->lds_elems);
   }
-  const LaunchCfg cands[] = {{512, 1}, {256, 1}, {512, 2}, {256, 2}};
+  std::vector<LaunchCfg> cands;
+  if (want < 0 || want == 2) {
+    for (int pc = 1; pc <= lds_kernel_per_cu(P); ++pc) {
+      cands.push_back({2, 256, pc});
+      cands.push_back({2, 512, pc});
+    }
+  }
+  if (want < 0 || want == 0) {
+    cands.push_back({0, 512, 1});
+    cands.push_back({0, 256, 1});
+    cands.push_back({0, 512, 2});
+    cands.push_back({0, 256, 2});
+  }
+  if (want < 0 || want == 1) cands.push_back({1, 256, 1});
   double* d_inner = nullptr;
   float* d_junc = nullptr;
   TTC_HIP(hipMalloc(&d_inner, sizeof(double) * std::max(P->n, 1)));
@@ -306,12 +354,12 @@ ttc_status autotune(ttc_plan* P) {
   TTC_HIP(hipEventCreate(&e1));
   float best_ms = 1e30f;
   for (const LaunchCfg& c : cands) {
-    int grid, lds;
-    TTC_TRY(upload_assignment(P, c, &grid, &lds));
-    BatchArgs a = make_args(P, P->d_begin, P->d_order, d_inner, d_junc, lds, grid);
-    TTC_HIP(launch_batch(P->dt, a, grid, c.threads, 0));
+    P->mode = c.mode;
+    P->cfg = c;
+    TTC_TRY(upload_assignment(P, c, &P->grid, &P->lds_elems));
+    TTC_HIP(run_mode(P, d_inner, d_junc, 0));
     TTC_HIP(hipEventRecord(e0, 0));
-    for (int r = 0; r < 2; ++r) TTC_HIP(launch_batch(P->dt, a, grid, c.threads, 0));
+    for (int r = 0; r < 2; ++r) TTC_HIP(run_mode(P, d_inner, d_junc, 0));
     TTC_HIP(hipEventRecord(e1, 0));
     TTC_HIP(hipEventSynchronize(e1));
     float ms = 0;
@@ -321,28 +369,13 @@ ttc_status autotune(ttc_plan* P) {
       best = c;
     }
   }
-  // the level-by-level schedule
-  P->mode = 1;
-  TTC_HIP(run_levels(P, d_inner, d_junc, 0));
-  TTC_HIP(hipEventRecord(e0, 0));
-  for (int r = 0; r < 2; ++r) TTC_HIP(run_levels(P, d_inner, d_junc, 0));
-  TTC_HIP(hipEventRecord(e1, 0));
-  TTC_HIP(hipEventSynchronize(e1));
-  float lv_ms = 0;
-  TTC_HIP(hipEventElapsedTime(&lv_ms, e0, e1));
-  P->mode = lv_ms < best_ms ? 1 : 0;
-  if (const char* fm = std::getenv("TTC_BATCH_MODE")) {  // forced schedule (testing)
-    if (std::strcmp(fm, "levels") == 0) P->mode = 1;
-    if (std::strcmp(fm, "persistent") == 0) P->mode = 0;
-  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   (void)hipFree(d_inner);
   (void)hipFree(d_junc);
+  P->mode = best.mode;
   P->cfg = best;
-  if (P->mode == 1) best.threads = -1;  // cache entry marks the level schedule
-  cache_store(key, best);
-  best.threads = P->cfg.threads;
+  if (!forced) cache_store(key, best);
   return upload_assignment(P, best, &P->grid, &P->lds_elems);
 }
 
@@ -375,6 +408,7 @@ ttc_status tt_batch_plan_create(const ttc_pair* pairs, int32_t n, uint32_t ops, 
   P->n = n;
   P->ops = ops;
   P->dt = dt;
+  P->buf_elems = 16 * (16 + 4);  // V_N = [1] padded
   const size_t esz = dt == TTC_BF16 ? 2 : 4;
   P->pairs.resize(n);
   P->joff.assign(n + 1, 0);
@@ -419,6 +453,7 @@ ttc_status tt_batch_plan_create(const ttc_pair* pairs, int32_t n, uint32_t ops, 
     P->bytes += by;
     P->cost[i] = fl_exec + 16.0 * by;  // FLOPs plus memory time at ~16 FLOP/byte
     for (int b = 1; b <= N; ++b) P->max_rp = std::max<long>(P->max_rp, (long)h.rx[b] * ((h.ry[b] & 1) ? h.ry[b] : h.ry[b] + 1));
+    for (int b = 1; b <= N; ++b) P->buf_elems = std::max(P->buf_elems, lds_iface_elems_h(h.rx[b], h.ry[b]));
   }
   hipError_t e = hipGetDevice(&P->device);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&P->cus, hipDeviceAttributeMultiprocessorCount, P->device);
@@ -480,6 +515,7 @@ ttc_status tt_batch_plan_create(const ttc_pair* pairs, int32_t n, uint32_t ops, 
   cp(P->d_01, zo, sizeof(zo));
   if (st == TTC_OK) {
     hipError_t ee = batch_set_lds(kLdsBytes);
+    if (ee == hipSuccess) ee = batch_lds_set_lds(2 * P->buf_elems * (int)sizeof(float));
     if (ee != hipSuccess) st = fail(TTC_ERR_HIP, std::string("kernel attribute: ") + hipGetErrorString(ee));
   }
   // level-by-level tables: items (pair, 16-row tile) of every level, heavy first
@@ -614,10 +650,10 @@ ttc_status tt_batch_run_plain(ttc_plan* P, double* d_inner, float* d_junction, v
   if ((P->ops & TTC_OP_INNER) && !d_inner) return fail(TTC_ERR_NULL, "d_inner is NULL");
   if ((P->ops & TTC_OP_SUFFIX2) && !d_junction) return fail(TTC_ERR_NULL, "d_junction is NULL");
   hipStream_t s = (hipStream_t)stream;
-  const int lds = kLdsBytes / (int)sizeof(float);
+  // one launch per pair of the LDS-resident kernel (one workgroup each)
   for (int p = 0; p < P->n; ++p) {
-    BatchArgs a = make_args(P, P->d_01, P->d_ident + p, d_inner, d_junction, lds, 1);
-    TTC_HIP(launch_batch(P->dt, a, 1, 512, s));
+    BatchArgs a = make_args(P, P->d_01, P->d_ident + p, d_inner, d_junction, 0, 1);
+    TTC_HIP(launch_batch_lds(P->dt, a, 1, 256, s));
   }
   return TTC_OK;
 }

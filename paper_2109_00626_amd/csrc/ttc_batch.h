@@ -28,6 +28,7 @@ struct BatchArgs {
   long t_stride;
   double* inner;
   float* junction;
+  int buf_elems;         // LDS-resident sweep: floats per interface buffer
 };
 
 // Level-by-level execution: one launch per step index from the right.
@@ -56,5 +57,7 @@ hipError_t level_set_lds(int level_bytes, int meet_bytes);
 hipError_t launch_level(ttc_dtype dt, const LevelArgs& a, int nitems, size_t lds, hipStream_t s);
 hipError_t launch_meet_level(ttc_dtype dt, const LevelArgs& a, int npairs, size_t lds, hipStream_t s);
 hipError_t launch_batch(ttc_dtype dt, const BatchArgs& a, int grid, int threads, hipStream_t s);
+hipError_t batch_lds_set_lds(int bytes);
+hipError_t launch_batch_lds(ttc_dtype dt, const BatchArgs& a, int grid, int threads, hipStream_t s);
 
 }  // namespace ttc

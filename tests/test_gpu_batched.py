@@ -1,4 +1,4 @@
-"""GPU parity of the batched persistent sweep (inner product + junction of
+"""GPU parity of the batched sweeps (inner product + junction of
 the contraction over the last two positions, per pair) against the FP64
 oracle, through the C ABI: a small uneven batch checked in full, and the
 4096-pair batch checked on sampled pairs (FP32 and BF16 inputs), against the
@@ -36,9 +36,9 @@ def _check_pairs(plan, inner, junc, cores64, idx, tol):
     return worst
 
 
-@pytest.fixture(params=["levels", "persistent"])
+@pytest.fixture(params=["lds", "levels", "persistent"])
 def batch_mode(request, monkeypatch):
-    """Both batched schedules (the autotuner picks one by timing)."""
+    """Every batched schedule (the autotuner picks one by timing)."""
     monkeypatch.setenv("TTC_BATCH_MODE", request.param)
     return request.param
 
