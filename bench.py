@@ -16,7 +16,8 @@ workload size, inputs resident in HBM:
 value = TT contractions per step / seconds per step.  Beside the step, the
 BF16 batch, the per-pair launch loop and the BF16-MFMA layer are timed once.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--parts ...]
+                       [--no-beside] [--copy-calibration MIB]
 """
 from __future__ import annotations
 
@@ -40,7 +41,40 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--parts", default="pair10,mpo8,batch,layer4")
+    ap.add_argument("--no-beside", action="store_true",
+                    help="skip the measurements beside the step (BF16 batch, plain loop, BF16 layer)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB mebibytes five times (counter calibration)")
     return ap.parse_args()
+
+
+# ------------------------------------------------------------- HBM traffic
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def kernel_source_digest(files):
+    """SHA-256 over the sources a kernel is built from (recorded with its
+    counter readings; a mismatch means the readings are stale)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter readings
+    (FETCH_SIZE + WRITE_SIZE, each scaled by the copy-kernel calibration), or
+    None when absent or taken on different kernel sources."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)["kernels"][kernel]
+    except (OSError, KeyError, ValueError):
+        return None
+    if kernel_source_digest(rec["sources"]) != rec["source_sha256"]:
+        return None
+    return rec["bytes_per_launch"]
 
 
 # ------------------------------------------------------------- workload setup
@@ -245,6 +279,16 @@ def main():
         sys.exit(2)
     import torch
 
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": 4 * n, "launches": 5}))
+        return
+
     import paper_2109_00626_amd as ttc
 
     parts = [p for p in args.parts.split(",") if p]
@@ -300,13 +344,17 @@ def main():
         ach = alg["layer4"]["fwd_flops"] / (gemm_ms * 1e-3) / 1e12
         roof = {"bound": "mfma", "kernel": "gemm_kernel (FP32 16x16x4 MFMA), measured as the whole forward call",
                 "achieved": round(ach, 2), "peak": PEAK["fp32_TFLOPs"], "unit": "TFLOP/s",
-                "frac": round(ach / PEAK["fp32_TFLOPs"], 4), "traffic": None,
+                "frac": round(ach / PEAK["fp32_TFLOPs"], 4), "traffic": recorded_traffic("gemm_kernel"),
                 "per_launch": "2 * 8192 * 4096 * 4096 FLOP (+ 1.1 GFLOP core chain)"}
     elif dominant == "batch":
         ms = part_ms["batch"]
         ach = alg["batch"]["bytes"] / (ms * 1e-3) / 1e9
-        roof = {"bound": "hbm", "kernel": "batch_kernel", "achieved": round(ach, 1), "peak": PEAK["hbm_GBs"],
-                "unit": "GB/s", "frac": round(ach / PEAK["hbm_GBs"], 4), "traffic": None}
+        cfg = W["batch"]["plan"].config
+        kname = {"lds": "batch_lds_kernel", "persistent": "batch_kernel", "levels": "level_kernel"}[cfg["mode"]]
+        roof = {"bound": "hbm", "kernel": kname, "schedule": cfg, "achieved": round(ach, 1),
+                "peak": PEAK["hbm_GBs"], "unit": "GB/s", "frac": round(ach / PEAK["hbm_GBs"], 4),
+                "traffic": recorded_traffic(f"{kname}/{cfg['threads']}") if cfg["mode"] == "lds" else None,
+                "per_launch": "all 4096 pairs: every core read once, 4096 FP64 scalars and the junctions written"}
     else:
         ms = part_ms[dominant]
         ach = alg[dominant]["bytes"] / (ms * 1e-3) / 1e9
@@ -314,7 +362,7 @@ def main():
                 "unit": "GB/s", "frac": round(ach / PEAK["hbm_GBs"], 4), "traffic": None}
 
     beside = {}
-    if "batch" in parts:
+    if "batch" in parts and not args.no_beside:
         d = W["batch"]
         plan = d["plan"]
 
@@ -346,7 +394,7 @@ def main():
                                 "GBs": round(plan_bf.bytes / (bf_ms * 1e-3) / 1e9, 1),
                                 "algorithmic_GB": round(plan_bf.bytes / 1e9, 3)}
         del pairs_bf, plan_bf, ib, jb
-    if "layer4" in parts:
+    if "layer4" in parts and not args.no_beside:
         d = W["layer4"]
 
         def layer(prec):

@@ -260,6 +260,11 @@ ttc_status tt_batch_plan_create(const ttc_pair* pairs, int32_t n, uint32_t ops, 
  * algorithmic FLOPs and bytes of one run (may be NULL). */
 ttc_status tt_batch_plan_info(const ttc_plan* plan, int64_t* junction_offsets, double* flops,
                               double* bytes);
+/* The schedule the plan's tuner selected (host ints; any may be NULL):
+ * mode 0 = persistent kernel with chained-MFMA steps, 1 = one launch per
+ * sweep level, 2 = persistent kernel with LDS-resident interfaces;
+ * threads = workgroup size; wg_per_cu = workgroups per compute unit. */
+ttc_status tt_batch_plan_config(const ttc_plan* plan, int32_t* mode, int32_t* threads, int32_t* wg_per_cu);
 ttc_status tt_batch_run(ttc_plan* plan, double* d_inner, float* d_junction, void* stream);
 /* The same pairs as one single-pair launch sequence each (the plain loop
  * that the batched launch replaces); same outputs. */

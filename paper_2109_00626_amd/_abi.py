@@ -71,6 +71,7 @@ def _declare(lib):
                                             c_void_p, c_size_t, c_void_p]),
         "tt_batch_plan_create": (c_int32, [P(Pair), c_int32, c_uint32, c_int32, P(c_void_p)]),
         "tt_batch_plan_info": (c_int32, [c_void_p, P(c_int64), P(c_double), P(c_double)]),
+        "tt_batch_plan_config": (c_int32, [c_void_p, P(c_int32), P(c_int32), P(c_int32)]),
         "tt_batch_run": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
         "tt_batch_run_plain": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
         "tt_batch_plan_destroy": (None, [c_void_p]),
@@ -101,6 +102,6 @@ EXPORTED = [
     "ttm_apply_dense_query", "ttm_apply_dense", "ttm_apply_dense_bwd",
     "ttc_mse_loss_query", "ttc_mse_loss",
     "tt_contract_inner_bwd_query", "tt_contract_inner_bwd",
-    "tt_batch_plan_create", "tt_batch_plan_info", "tt_batch_run", "tt_batch_run_plain",
+    "tt_batch_plan_create", "tt_batch_plan_info", "tt_batch_plan_config", "tt_batch_run", "tt_batch_run_plain",
     "tt_batch_plan_destroy",
 ]

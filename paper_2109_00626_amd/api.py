@@ -296,6 +296,9 @@ class BatchPlan:
         _check(_lib.tt_batch_plan_info(self._h, offs, byref(fl), byref(by)))
         self.junction_offsets = list(offs)
         self.flops, self.bytes = fl.value, by.value
+        m, t, pc = c_int32(), c_int32(), c_int32()
+        _check(_lib.tt_batch_plan_config(self._h, byref(m), byref(t), byref(pc)))
+        self.config = {"mode": ("persistent", "levels", "lds")[m.value], "threads": t.value, "wg_per_cu": pc.value}
 
     def outputs(self):
         inner = torch.empty(self.n, dtype=torch.float64, device=self.device)

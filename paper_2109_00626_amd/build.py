@@ -1,6 +1,6 @@
 """Build libttc.so (all HIP kernels and the host runtime) for gfx950 with hipcc.
 
-Every call recompiles every source.  Usage: python -m paper_2109_00626_amd.build
+Every call recompiles every source.  Usage: python paper_2109_00626_amd/build.py
 """
 from __future__ import annotations
 

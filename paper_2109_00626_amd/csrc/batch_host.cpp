@@ -611,6 +611,14 @@ ttc_status tt_batch_plan_info(const ttc_plan* P, int64_t* junction_offsets, doub
   return TTC_OK;
 }
 
+ttc_status tt_batch_plan_config(const ttc_plan* P, int32_t* mode, int32_t* threads, int32_t* wg_per_cu) {
+  if (!P) return fail(TTC_ERR_NULL, "plan is NULL");
+  if (mode) *mode = P->mode;
+  if (threads) *threads = P->cfg.threads;
+  if (wg_per_cu) *wg_per_cu = P->cfg.per_cu;
+  return TTC_OK;
+}
+
 ttc_status tt_batch_run(ttc_plan* P, double* d_inner, float* d_junction, void* stream) {
   if (!P) return fail(TTC_ERR_NULL, "plan is NULL");
   if ((P->ops & TTC_OP_INNER) && !d_inner) return fail(TTC_ERR_NULL, "d_inner is NULL");

@@ -96,10 +96,11 @@ struct Raw4<float> {
     return f32x4{__uint_as_float(v[0]), __uint_as_float(v[1]), __uint_as_float(v[2]), __uint_as_float(v[3])};
   }
   __device__ __forceinline__ static float get(const f32x4& v, int u) { return v[u]; }
-  // elements u with keep[u] false set to zero
-  __device__ __forceinline__ static f32x4 mask(const f32x4& v, const bool keep[4]) {
+  // as FP32, elements u with keep[u] false set to zero
+  __device__ __forceinline__ static f32x4 to_f32(const f32x4& v, const bool keep[4]) {
     return f32x4{keep[0] ? v[0] : 0.f, keep[1] ? v[1] : 0.f, keep[2] ? v[2] : 0.f, keep[3] ? v[3] : 0.f};
   }
+  __device__ __forceinline__ static f32x4 to_f32(const f32x4& v) { return v; }
 };
 template <>
 struct Raw4<bf16_t> {
@@ -116,10 +117,12 @@ struct Raw4<bf16_t> {
     const unsigned w = (u < 2) ? v.x : v.y;
     return __uint_as_float((u & 1) ? (w & 0xFFFF0000u) : (w << 16));
   }
-  __device__ __forceinline__ static uint2 mask(const uint2& v, const bool keep[4]) {
-    const unsigned x = (keep[0] ? 0x0000FFFFu : 0u) | (keep[1] ? 0xFFFF0000u : 0u);
-    const unsigned y = (keep[2] ? 0x0000FFFFu : 0u) | (keep[3] ? 0xFFFF0000u : 0u);
-    return make_uint2(v.x & x, v.y & y);
+  __device__ __forceinline__ static f32x4 to_f32(const uint2& v, const bool keep[4]) {
+    return f32x4{keep[0] ? get(v, 0) : 0.f, keep[1] ? get(v, 1) : 0.f, keep[2] ? get(v, 2) : 0.f,
+                 keep[3] ? get(v, 3) : 0.f};
+  }
+  __device__ __forceinline__ static f32x4 to_f32(const uint2& v) {
+    return f32x4{get(v, 0), get(v, 1), get(v, 2), get(v, 3)};
   }
 };
 
@@ -159,20 +162,24 @@ __device__ __forceinline__ void lds_tile(const StepOp& op, const TTC_LDS float* 
   const TTC_LDS float* inl = In + li * ip + 4 * g;
   if (s0 >= I) return;
 
-  raw_t bx[KC], bxn[KC], gv[PT], gvn[PT];
+  // current operands as FP32 (masked), next ones as loaded
+  f32x4 bx[KC], gv[PT];
+  raw_t bxn[KC], gvn[PT];
   {
     const CoreRes ra = core_rsrc(op.ga, (long)s0 * Ka, ta, esz);
     const CoreRes rb = core_rsrc(op.gb, (long)s0 * Kb, tb, esz);
 #pragma unroll
-    for (int kc = 0; kc < KC; ++kc) bx[kc] = R4::load(ra, aoff + kc * 16 * esz);
+    for (int kc = 0; kc < KC; ++kc) bxn[kc] = R4::load(ra, aoff + kc * 16 * esz);
 #pragma unroll
-    for (int pt = 0; pt < PT; ++pt) gv[pt] = R4::load(rb, boff[pt]);
+    for (int pt = 0; pt < PT; ++pt) gvn[pt] = R4::load(rb, boff[pt]);
     bool mb[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) mb[v] = 4 * g + v < Kb;
-    bx[KC - 1] = R4::mask(bx[KC - 1], ma);
 #pragma unroll
-    for (int pt = 0; pt < PT; ++pt) gv[pt] = R4::mask(gv[pt], mb);
+    for (int kc = 0; kc < KC - 1; ++kc) bx[kc] = R4::to_f32(bxn[kc]);
+    bx[KC - 1] = R4::to_f32(bxn[KC - 1], ma);
+#pragma unroll
+    for (int pt = 0; pt < PT; ++pt) gv[pt] = R4::to_f32(gvn[pt], mb);
     // all prologue loads done here, so no load issued before the loop is
     // still counted as pending inside it
     __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
@@ -203,23 +210,23 @@ __device__ __forceinline__ void lds_tile(const StepOp& op, const TTC_LDS float* 
 #pragma unroll
     for (int kc = 0; kc < KC; ++kc)
 #pragma unroll
-      for (int u = 0; u < 4; ++u) st = mfma4(av[kc][u], R4::get(bx[kc], u), st);
+      for (int u = 0; u < 4; ++u) st = mfma4(av[kc][u], bx[kc][u], st);
     // Out[a-tile, b-tile pt] += S_i[:, qt-slice] . G_B[b-tile, i, qt-slice]^T
 #pragma unroll
     for (int pt = 0; pt < PT; ++pt)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) acc[pt] = mfma4(st[v], R4::get(gv[pt], v), acc[pt]);
+      for (int v = 0; v < 4; ++v) acc[pt] = mfma4(st[v], gv[pt][v], acc[pt]);
     if (!more) break;
     // the prefetched operands become current (masked past the row ends)
     bool mb[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) mb[v] = nq * 16 + 4 * g + v < Kb;
 #pragma unroll
-    for (int pt = 0; pt < PT; ++pt) gv[pt] = R4::mask(gvn[pt], mb);
+    for (int pt = 0; pt < PT; ++pt) gv[pt] = R4::to_f32(gvn[pt], mb);
     if (nq == 0) {
 #pragma unroll
-      for (int kc = 0; kc < KC - 1; ++kc) bx[kc] = bxn[kc];
-      bx[KC - 1] = R4::mask(bxn[KC - 1], ma);
+      for (int kc = 0; kc < KC - 1; ++kc) bx[kc] = R4::to_f32(bxn[kc]);
+      bx[KC - 1] = R4::to_f32(bxn[KC - 1], ma);
     }
     i = ni;
     qt = nq;
