@@ -1,90 +1,222 @@
 // TT-matrix (MPO) x TT-vector on cores:
 //   C^(k)[(a,r), i, (a',r')] = sum_j W^(k)[a, i, j, a'] V^(k)[r, j, r'].
-// For a fixed (a, i, r) the output row over (a', r') is contiguous, so one
-// workgroup owns (core, a, i) and walks r: per r the product
-//   D[r', a'] = sum_j V[r, j, r'] W[a, i, j, a']
-// is a small GEMM (M = r', N = a', K = j) on 16x16x32 BF16 MFMA tiles with
-// FP32 accumulation.  Both operands are staged in LDS with j contiguous, so
-// every lane feeds the MFMA with one 16-byte read; every lane then writes 4
-// consecutive r' of the output with one non-temporal 16-byte store.  The
-// kernel is bound by the HBM write of the output (its entries outnumber the
-// inputs' by orders of magnitude).
+// The output outnumbers the inputs by orders of magnitude (ranks multiply),
+// so the kernel is a streaming writer.  One wave owns one (core, a, r): its
+// output is the contiguous block C[(a,r), :, :] of I x a1 x r1 values.  The
+// wave stages V[r, :, :] once in LDS as Vt[r'][j], and per mode index i the
+// slice W[a, i, :, :] as Wt[a'][j] (loaded four indices ahead into registers),
+// forms D_i[a', r'] = sum_j Wt[a'][j] Vt[r'][j] on 16x16 MFMA tiles (BF16
+// inputs: 16x16x32 BF16; FP32 inputs: 16x16x4 FP32; FP32 accumulation), and
+// writes D_i through a small LDS buffer so that every global store is 64
+// lanes x 16 contiguous bytes, non-temporal.  Waves are independent (no
+// barriers: LDS operations of one wave complete in order, and a compiler
+// memory barrier keeps the staging writes and the differently typed operand
+// reads in program order); LDS rows are padded with zeros to the MFMA's K
+// step.
 #include "ttc_device.hpp"
 #include "ttc_internal.h"
+
+#include <algorithm>
 
 namespace ttc {
 
 #define MPO_WAVES 4
+#define MPO_PREF 8   // W elements per lane prefetched per index (the rest loads in place)
+#define MPO_DEPTH 4  // indices of W prefetched ahead
+#define MPO_COPY 8   // 16-byte output chunks per lane with precomputed LDS offsets
 
-template <typename Tin, typename Tc>
-__device__ __forceinline__ const MpoCore& find_core(const MpoArgs& a, int blk) {
+// Compiler-only memory barrier (no instruction): LDS written through one
+// element type and read through another must not be reordered.
+#define MPO_ORDER() asm volatile("" ::: "memory")
+
+template <typename Tin>
+struct MpoT;
+template <>
+struct MpoT<bf16_t> {
+  typedef uint16_t E;
+  static constexpr int KB = 32;  // K of one MFMA
+  static constexpr int PAD = 8;  // LDS row padding (elements)
+};
+template <>
+struct MpoT<float> {
+  typedef float E;
+  static constexpr int KB = 4;
+  static constexpr int PAD = 4;
+};
+
+// Per-wave LDS layout of one core (elements of E, then floats).
+struct MpoLds {
+  int Jp, pitch, a1p, r1p, dp;
+  long vt, wt, dl;  // byte offsets within the wave's region
+  long bytes;
+};
+template <typename Tin>
+__host__ __device__ inline MpoLds mpo_lds(int J, int a1, int r1) {
+  typedef MpoT<Tin> T;
+  MpoLds L;
+  L.Jp = (J + T::KB - 1) / T::KB * T::KB;
+  L.pitch = L.Jp + T::PAD;
+  L.a1p = (a1 + 15) / 16 * 16;
+  L.r1p = (r1 + 15) / 16 * 16;
+  L.dp = L.r1p + 4;
+  L.vt = 0;
+  L.wt = L.vt + (long)L.r1p * L.pitch * (long)sizeof(typename T::E);
+  L.wt = (L.wt + 15) & ~15L;
+  L.dl = L.wt + (long)L.a1p * L.pitch * (long)sizeof(typename T::E);
+  L.dl = (L.dl + 15) & ~15L;
+  L.bytes = L.dl + (long)L.a1p * L.dp * 4 + 16;  // + a dummy slot for masked staging writes
+  return L;
+}
+
+__device__ __forceinline__ const MpoCore& mpo_core_of(const MpoArgs& a, int item) {
   int c = 0;
-  while (c + 1 < a.ncores && a.c[c + 1].blk_begin <= blk) ++c;
+  while (c + 1 < a.ncores && a.c[c + 1].blk_begin <= item) ++c;
   return a.c[c];
 }
 
-// LDS row pitch (in bf16) for j: padded to a multiple of 32 plus 8 to spread banks.
-__host__ __device__ __forceinline__ int mpo_pitch(int J) { return ((J + 31) / 32) * 32 + 8; }
-
-__global__ __launch_bounds__(256) void mpo_bf16_kernel(MpoArgs a) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  const MpoCore& c = find_core<bf16_t, float>(a, blockIdx.x);
-  const int local = blockIdx.x - c.blk_begin;
-  const int a_idx = local / c.I, i = local - a_idx * c.I;
-  const int J = c.J, a1 = c.a1, r0 = c.r0, r1 = c.r1;
-  const int pitch = mpo_pitch(J);
-  const int Jp = ((J + 31) / 32) * 32;
-  const int a1p = ((a1 + 15) / 16) * 16, r1p = ((r1 + 15) / 16) * 16;
-  uint16_t* Wt = reinterpret_cast<uint16_t*>(smem);              // [a1p][pitch]
-  uint16_t* Vt = Wt + a1p * pitch;                               // [MPO_WAVES][r1p][pitch]
-  const uint16_t* Wsrc = reinterpret_cast<const uint16_t*>(c.w) + ((long)a_idx * c.I + i) * J * a1;
-  const uint16_t* Vsrc = reinterpret_cast<const uint16_t*>(c.v);
-  // stage W[a, i, :, :] transposed: Wt[a'][j]
-  for (int e = threadIdx.x; e < a1p * Jp; e += blockDim.x) {
-    const int ap = e / Jp, j = e - ap * Jp;
-    Wt[ap * pitch + j] = (ap < a1 && j < J) ? Wsrc[(long)j * a1 + ap] : (uint16_t)0;
-  }
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int li = lane & 15, g = lane >> 4;
-  const long row_len = (long)a1 * r1;
-  float* out_base = reinterpret_cast<float*>(c.out);
-  const int tn = a1p / 16, tm = r1p / 16;
-  for (int rb = 0; rb < r0; rb += MPO_WAVES) {
-    __syncthreads();
-    // stage V[r, :, :] transposed for the MPO_WAVES rows of this round
-    for (int e = threadIdx.x; e < MPO_WAVES * r1p * Jp; e += blockDim.x) {
-      const int w = e / (r1p * Jp);
-      const int rem = e - w * r1p * Jp;
-      const int j = rem / r1p, rp = rem - j * r1p;  // rp fastest: coalesced global reads
-      const int r = rb + w;
-      uint16_t v = 0;
-      if (r < r0 && rp < r1 && j < J) v = Vsrc[((long)r * J + j) * r1 + rp];
-      Vt[(w * r1p + rp) * pitch + j] = v;
+template <typename Tin>
+__device__ __forceinline__ f32x4 mpo_tile(const typename MpoT<Tin>::E* Vt, const typename MpoT<Tin>::E* Wt, int pitch,
+                                          int Jp, int rt, int at, int li, int g) {
+  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  if constexpr (sizeof(Tin) == 2) {
+    for (int k0 = 0; k0 < Jp; k0 += 32) {
+      const bf16x8 av = *reinterpret_cast<const bf16x8*>(Vt + (rt * 16 + li) * pitch + k0 + 8 * g);
+      const bf16x8 bv = *reinterpret_cast<const bf16x8*>(Wt + (at * 16 + li) * pitch + k0 + 8 * g);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
     }
-    __syncthreads();
-    const int r = rb + wave;
-    if (r >= r0) continue;
-    float* orow = out_base + (((long)a_idx * r0 + r) * c.I + i) * row_len;
-    const uint16_t* Vw = Vt + wave * r1p * pitch;
-    for (int tt = 0; tt < tm * tn; ++tt) {
-      const int m0 = (tt / tn) * 16, n0 = (tt % tn) * 16;
-      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-      for (int k0 = 0; k0 < Jp; k0 += 32) {
-        const bf16x8 av = *reinterpret_cast<const bf16x8*>(Vw + (m0 + li) * pitch + k0 + 8 * g);
-        const bf16x8 bv = *reinterpret_cast<const bf16x8*>(Wt + (n0 + li) * pitch + k0 + 8 * g);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
+  } else {
+    for (int k0 = 0; k0 < Jp; k0 += 4) {
+      const float av = Vt[(rt * 16 + li) * pitch + k0 + g];
+      const float bv = Wt[(at * 16 + li) * pitch + k0 + g];
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
+    }
+  }
+  return acc;
+}
+
+// FIT: every core's W slice has at most 64 * MPO_PREF elements and every
+// output row at most 256 * MPO_COPY, so the main loop has no loops of
+// runtime length around memory operations (their unknown counts would force
+// waits for every outstanding load and store).
+template <typename Tin, bool FIT>
+__global__ __launch_bounds__(64 * MPO_WAVES) void mpo_stream_kernel(MpoArgs a, int wave_bytes) {
+  typedef typename MpoT<Tin>::E E;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wave
+  const int li = lane & 15, g = lane >> 4;
+  const int item = blockIdx.x * MPO_WAVES + wave;
+  if (item >= a.nblk) return;  // whole waves only: no barriers follow
+  const MpoCore& c = mpo_core_of(a, item);
+  const int local = item - c.blk_begin;
+  const int aa = local / c.r0, r = local - aa * c.r0;
+  const int I = c.I, J = c.J, a1 = c.a1, r1 = c.r1;
+  const MpoLds L = mpo_lds<Tin>(J, a1, r1);
+  unsigned char* base = smem + (long)wave * wave_bytes;
+  E* Vt = reinterpret_cast<E*>(base + L.vt);
+  E* Wt = reinterpret_cast<E*>(base + L.wt);
+  float* Dl = reinterpret_cast<float*>(base + L.dl);
+  const E* Vg = reinterpret_cast<const E*>(c.v) + (long)r * J * r1;
+  const E* Wg = reinterpret_cast<const E*>(c.w) + (long)aa * I * J * a1;
+  float* out = reinterpret_cast<float*>(c.out) + (long)(aa * c.r0 + r) * I * a1 * r1;
+  // zero both staging tiles (padding stays zero), then V[r] as Vt[r'][j]
+  for (int e = lane; e < L.r1p * L.pitch; e += 64) Vt[e] = (E)0;
+  for (int e = lane; e < L.a1p * L.pitch; e += 64) Wt[e] = (E)0;
+  for (int e = lane; e < J * r1; e += 64) {
+    const int j = e / r1, rp = e - j * r1;
+    Vt[rp * L.pitch + j] = Vg[e];
+  }
+  MPO_ORDER();
+  const int JA = J * a1;
+  // W slices run MPO_DEPTH indices ahead in a register ring (the loop below
+  // is unrolled by MPO_DEPTH so every slot index is static); the LDS offsets
+  // of the prefetched elements are the same for every index
+  E pf[MPO_DEPTH][MPO_PREF];
+  int woff[MPO_PREF];
+  // (elements past the slice load a valid address and land in a dummy LDS
+  // slot, so staging has no branches and no early waits)
+  const int dummy = (int)((L.dl + (long)L.a1p * L.dp * 4 - L.wt) / (long)sizeof(E));
+  int eoff[MPO_PREF];
+#pragma unroll
+  for (int t = 0; t < MPO_PREF; ++t) {
+    const int e = lane + 64 * t;
+    const int j = e / a1, ap = e - j * a1;
+    woff[t] = (e < JA) ? ap * L.pitch + j : dummy;
+    eoff[t] = min(e, JA - 1);
+  }
+#pragma unroll
+  for (int d = 0; d < MPO_DEPTH; ++d)
+#pragma unroll
+    for (int t = 0; t < MPO_PREF; ++t) pf[d][t] = Wg[(long)min(d, I - 1) * JA + eoff[t]];
+  const int RT = L.r1p / 16, AT = L.a1p / 16;
+  const int n = a1 * r1;
+  const bool vec = (r1 % 4 == 0) && ((reinterpret_cast<uintptr_t>(out) & 15) == 0);
+  // LDS offsets of the lane's copy-out chunks (vector path, first MPO_COPY)
+  int doff[MPO_COPY];
+#pragma unroll
+  for (int q = 0; q < MPO_COPY; ++q) {
+    const int e = 4 * lane + 256 * q;
+    const int ap = e / r1, rp = e - ap * r1;
+    doff[q] = ap * L.dp + rp;
+  }
+  for (int i0 = 0; i0 < I; i0 += MPO_DEPTH) {
+#pragma unroll
+    for (int d = 0; d < MPO_DEPTH; ++d) {
+      const int i = i0 + d;
+      if (i >= I) break;
+      // W[a, i] into Wt[a'][j]: the prefetched part, then any remainder
+#pragma unroll
+      for (int t = 0; t < MPO_PREF; ++t) Wt[woff[t]] = pf[d][t];
+      if constexpr (!FIT)
+        for (int e = lane + 64 * MPO_PREF; e < JA; e += 64) {
+          const int j = e / a1, ap = e - j * a1;
+          Wt[ap * L.pitch + j] = Wg[(long)i * JA + e];
+        }
+      MPO_ORDER();
+      if (i + MPO_DEPTH < I) {
+        const E* src = Wg + (long)(i + MPO_DEPTH) * JA;
+#pragma unroll
+        for (int t = 0; t < MPO_PREF; ++t) pf[d][t] = src[eoff[t]];
       }
-      const int ap = n0 + li;      // a'
-      const int rp = m0 + 4 * g;   // first of 4 consecutive r'
-      if (ap < a1) {
-        float* q = orow + (long)ap * r1 + rp;
-        if (rp + 3 < r1 && (r1 & 3) == 0) {
-          __builtin_nontemporal_store(acc, reinterpret_cast<f32x4*>(q));
-        } else {
-          for (int v = 0; v < 4; ++v)
-            if (rp + v < r1) q[v] = acc[v];
+      // D_i tiles -> Dl[a'][r']
+      for (int at = 0; at < AT; ++at)
+        for (int rt = 0; rt < RT; ++rt) {
+          const f32x4 acc = mpo_tile<Tin>(Vt, Wt, L.pitch, L.Jp, rt, at, li, g);
+          *reinterpret_cast<f32x4*>(Dl + (at * 16 + li) * L.dp + rt * 16 + 4 * g) = acc;
+        }
+      MPO_ORDER();
+      // contiguous copy-out of the a1 x r1 block of index i
+      float* orow = out + (long)i * n;
+      if (vec) {
+#pragma unroll
+        for (int q = 0; q < MPO_COPY; ++q) {
+          const int e = 4 * lane + 256 * q;
+          if (e < n)
+            __builtin_nontemporal_store(*reinterpret_cast<const f32x4*>(Dl + doff[q]),
+                                        reinterpret_cast<f32x4*>(orow + e));
+        }
+        if constexpr (!FIT)
+          for (int e = 4 * lane + 256 * MPO_COPY; e < n; e += 256) {
+            const int ap = e / r1, rp = e - ap * r1;
+            const f32x4 v = *reinterpret_cast<const f32x4*>(Dl + ap * L.dp + rp);
+            __builtin_nontemporal_store(v, reinterpret_cast<f32x4*>(orow + e));
+          }
+      } else if constexpr (FIT) {
+#pragma unroll
+        for (int q = 0; q < 4 * MPO_COPY; ++q) {
+          const int e = lane + 64 * q;
+          if (e < n) {
+            const int ap = e / r1, rp = e - ap * r1;
+            __builtin_nontemporal_store(Dl[ap * L.dp + rp], orow + e);
+          }
+        }
+      } else {
+        for (int e = lane; e < n; e += 64) {
+          const int ap = e / r1, rp = e - ap * r1;
+          __builtin_nontemporal_store(Dl[ap * L.dp + rp], orow + e);
         }
       }
+      MPO_ORDER();
     }
   }
 }
@@ -92,7 +224,7 @@ __global__ __launch_bounds__(256) void mpo_bf16_kernel(MpoArgs a) {
 // Any dtype, plain FMA: one thread per output entry.
 template <typename Tin, typename Tc>
 __global__ __launch_bounds__(256) void mpo_generic_kernel(MpoArgs a) {
-  const MpoCore& c = find_core<Tin, Tc>(a, blockIdx.x);
+  const MpoCore& c = mpo_core_of(a, blockIdx.x);
   const long per = (long)c.a0 * c.r0 * c.I * c.a1 * c.r1;
   const long e = (long)(blockIdx.x - c.blk_begin) * blockDim.x + threadIdx.x;
   if (e >= per) return;
@@ -110,41 +242,56 @@ __global__ __launch_bounds__(256) void mpo_generic_kernel(MpoArgs a) {
   reinterpret_cast<Tc*>(c.out)[e] = acc;
 }
 
-size_t mpo_bf16_lds(const MpoArgs& a) {
-  size_t mx = 0;
+// Per-wave LDS bytes of the streaming kernel for the largest core.
+template <typename Tin>
+long mpo_wave_bytes(const MpoArgs& a) {
+  long mx = 0;
+  for (int k = 0; k < a.ncores; ++k) mx = std::max(mx, mpo_lds<Tin>(a.c[k].J, a.c[k].a1, a.c[k].r1).bytes);
+  return (mx + 15) & ~15L;
+}
+
+template <typename Tin, bool FIT>
+hipError_t launch_mpo_stream_as(const MpoArgs& a, int items, long wb, hipStream_t s) {
+  const int lds = (int)(wb * MPO_WAVES);
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&mpo_stream_kernel<Tin, FIT>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((mpo_stream_kernel<Tin, FIT>), dim3((items + MPO_WAVES - 1) / MPO_WAVES), dim3(64 * MPO_WAVES),
+                     (size_t)lds, s, a, (int)wb);
+  return hipGetLastError();
+}
+
+template <typename Tin>
+hipError_t launch_mpo_stream(MpoArgs a, hipStream_t s) {
+  const long wb = mpo_wave_bytes<Tin>(a);
+  int items = 0;
+  bool fit = true;
   for (int k = 0; k < a.ncores; ++k) {
-    const MpoCore& c = a.c[k];
-    const int pitch = mpo_pitch(c.J);
-    const size_t b = ((size_t)((c.a1 + 15) / 16) * 16 + (size_t)MPO_WAVES * ((c.r1 + 15) / 16) * 16) * pitch * 2;
-    if (b > mx) mx = b;
+    a.c[k].blk_begin = items;
+    items += a.c[k].a0 * a.c[k].r0;
+    fit = fit && a.c[k].J * a.c[k].a1 <= 64 * MPO_PREF && a.c[k].a1 * a.c[k].r1 <= 256 * MPO_COPY;
   }
-  return mx;
+  a.nblk = items;
+  if (items <= 0) return hipSuccess;
+  return fit ? launch_mpo_stream_as<Tin, true>(a, items, wb, s) : launch_mpo_stream_as<Tin, false>(a, items, wb, s);
 }
 
 hipError_t launch_mpo(ttc_dtype dt, bool bf16_mfma, const MpoArgs& in, hipStream_t s) {
+  (void)bf16_mfma;  // BF16 inputs always use BF16 MFMA with FP32 accumulation
+  if (dt == TTC_BF16 && mpo_wave_bytes<bf16_t>(in) * MPO_WAVES <= lds_limit_bytes())
+    return launch_mpo_stream<bf16_t>(in, s);
+  if (dt == TTC_F32 && mpo_wave_bytes<float>(in) * MPO_WAVES <= lds_limit_bytes())
+    return launch_mpo_stream<float>(in, s);
   MpoArgs a = in;
-  const size_t lds = bf16_mfma ? mpo_bf16_lds(a) : 0;
-  const bool use_mfma = bf16_mfma && dt == TTC_BF16 && lds <= (size_t)lds_limit_bytes();
   int nblk = 0;
   for (int k = 0; k < a.ncores; ++k) {
     MpoCore& c = a.c[k];
     c.blk_begin = nblk;
-    if (use_mfma) {
-      nblk += c.a0 * c.I;
-    } else {
-      const long per = (long)c.a0 * c.r0 * c.I * c.a1 * c.r1;
-      nblk += (int)((per + 255) / 256);
-    }
+    const long per = (long)c.a0 * c.r0 * c.I * c.a1 * c.r1;
+    nblk += (int)((per + 255) / 256);
   }
   a.nblk = nblk;
   if (nblk <= 0) return hipSuccess;
-  if (use_mfma) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&mpo_bf16_kernel),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(mpo_bf16_kernel, dim3(nblk), dim3(64 * MPO_WAVES), lds, s, a);
-    return hipGetLastError();
-  }
   switch (dt) {
     case TTC_F64: hipLaunchKernelGGL((mpo_generic_kernel<double, double>), dim3(nblk), dim3(256), 0, s, a); break;
     case TTC_F32: hipLaunchKernelGGL((mpo_generic_kernel<float, float>), dim3(nblk), dim3(256), 0, s, a); break;

@@ -224,6 +224,22 @@ def test_mpo_small_dtypes(ttc):
     assert all(torch.equal(a, b) for a, b in zip(out, vg))
 
 
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_mpo_tiles_and_tails(ttc, dtype):
+    """Several MFMA tiles along a' and r', K chunks with a ragged tail (J = 40,
+    33), row lengths with and without vector stores (r' = 20, 8, 1), and a
+    W slice larger than the per-lane prefetch (J * a' = 1200)."""
+    sw = C.TTShape([3, 2, 4], [1, 30, 3, 1], [40, 5, 33])
+    sv = C.TTShape([40, 5, 33], [1, 20, 8, 1])
+    w = C.gen_tt_np(43, 1, sw)
+    v = C.gen_tt_np(43, 2, sv)
+    wg, ws = to_gpu(w, dtype)
+    vg, vs = to_gpu(v, dtype)
+    out = [to_np(t) for t in ttc.ttm_apply(wg, vg)]
+    want = O.mpo_tt(ws, vs) if dtype == "f32" else O.mpo_tt(w, v)
+    assert max_core_rel(out, want) <= TOL[dtype]
+
+
 def test_mpo8_bf16_full(ttc):
     """Order-8 MPO (I = J = 32, rank 16) on an order-8 TT (mode 32, rank 64),
     BF16 inputs, FP32 output with ranks 1024; against the FP64 oracle on the
