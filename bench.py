@@ -350,10 +350,11 @@ def main():
         ms = part_ms["batch"]
         ach = alg["batch"]["bytes"] / (ms * 1e-3) / 1e9
         cfg = W["batch"]["plan"].config
-        kname = {"lds": "batch_lds_kernel", "persistent": "batch_kernel", "levels": "level_kernel"}[cfg["mode"]]
+        kname = {"lds": "batch_lds_kernel", "lds1": "batch_lds_kernel_inplace", "persistent": "batch_kernel",
+                 "levels": "level_kernel"}[cfg["mode"]]
         roof = {"bound": "hbm", "kernel": kname, "schedule": cfg, "achieved": round(ach, 1),
                 "peak": PEAK["hbm_GBs"], "unit": "GB/s", "frac": round(ach / PEAK["hbm_GBs"], 4),
-                "traffic": recorded_traffic(f"{kname}/{cfg['threads']}") if cfg["mode"] == "lds" else None,
+                "traffic": recorded_traffic(f"{kname}/{cfg['threads']}") if cfg["mode"] in ("lds", "lds1") else None,
                 "per_launch": "all 4096 pairs: every core read once, 4096 FP64 scalars and the junctions written"}
     else:
         ms = part_ms[dominant]

@@ -262,13 +262,24 @@ ttc_status tt_batch_plan_info(const ttc_plan* plan, int64_t* junction_offsets, d
                               double* bytes);
 /* The schedule the plan's tuner selected (host ints; any may be NULL):
  * mode 0 = persistent kernel with chained-MFMA steps, 1 = one launch per
- * sweep level, 2 = persistent kernel with LDS-resident interfaces;
+ * sweep level, 2 = persistent kernel with LDS-resident interfaces, 3 = the
+ * same with one interface buffer per workgroup updated in place;
  * threads = workgroup size; wg_per_cu = workgroups per compute unit. */
 ttc_status tt_batch_plan_config(const ttc_plan* plan, int32_t* mode, int32_t* threads, int32_t* wg_per_cu);
 ttc_status tt_batch_run(ttc_plan* plan, double* d_inner, float* d_junction, void* stream);
 /* The same pairs as one single-pair launch sequence each (the plain loop
  * that the batched launch replaces); same outputs. */
 ttc_status tt_batch_run_plain(ttc_plan* plan, double* d_inner, float* d_junction, void* stream);
+/* tt_batch_run with tracing: the same outputs, plus GPU clock readings
+ * (s_memtime, shader cycles; comparable within one workgroup) in d_clock, a
+ * device int64 array of 35 n entries: for pair p, d_clock[2p] and
+ * d_clock[2p+1] are when its workgroup started and finished it,
+ * d_clock[2n + p] is that workgroup, and d_clock[3n + 32p + j] the clock
+ * after sweep step j (j = 0 .. N-2, right to left) and, at j = N-1, after
+ * the final product.  Launched directly (not from the plan's graph); for
+ * load-balance and per-step cost analysis. */
+ttc_status tt_batch_run_traced(ttc_plan* plan, double* d_inner, float* d_junction, int64_t* d_clock,
+                               void* stream);
 void tt_batch_plan_destroy(ttc_plan* plan);
 
 /* ------------------------------------------------------------------------ */

@@ -74,6 +74,7 @@ def _declare(lib):
         "tt_batch_plan_config": (c_int32, [c_void_p, P(c_int32), P(c_int32), P(c_int32)]),
         "tt_batch_run": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
         "tt_batch_run_plain": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
+        "tt_batch_run_traced": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
         "tt_batch_plan_destroy": (None, [c_void_p]),
     }
     for name, (res, args) in sig.items():
@@ -83,10 +84,12 @@ def _declare(lib):
     return sig
 
 
-def load(path: str = LIB_PATH):
+def load(path: str = None):
+    # TTC_LIBRARY selects another build of the same library (for comparing builds)
+    path = path or os.environ.get("TTC_LIBRARY") or LIB_PATH
     if not os.path.exists(path):
         raise ImportError(
-            f"libttc.so not found at {path}: build it first (python -m paper_2109_00626_amd.build "
+            f"libttc.so not found at {path}: build it first (python paper_2109_00626_amd/build.py "
             "or __graft_entry__.build()); there is no fallback implementation")
     lib = ctypes.CDLL(path)
     _declare(lib)
@@ -103,5 +106,6 @@ EXPORTED = [
     "ttc_mse_loss_query", "ttc_mse_loss",
     "tt_contract_inner_bwd_query", "tt_contract_inner_bwd",
     "tt_batch_plan_create", "tt_batch_plan_info", "tt_batch_plan_config", "tt_batch_run", "tt_batch_run_plain",
+    "tt_batch_run_traced",
     "tt_batch_plan_destroy",
 ]

@@ -298,7 +298,7 @@ class BatchPlan:
         self.flops, self.bytes = fl.value, by.value
         m, t, pc = c_int32(), c_int32(), c_int32()
         _check(_lib.tt_batch_plan_config(self._h, byref(m), byref(t), byref(pc)))
-        self.config = {"mode": ("persistent", "levels", "lds")[m.value], "threads": t.value, "wg_per_cu": pc.value}
+        self.config = {"mode": ("persistent", "levels", "lds", "lds1")[m.value], "threads": t.value, "wg_per_cu": pc.value}
 
     def outputs(self):
         inner = torch.empty(self.n, dtype=torch.float64, device=self.device)
@@ -311,6 +311,19 @@ class BatchPlan:
         f = _lib.tt_batch_run_plain if plain else _lib.tt_batch_run
         _check(f(self._h, _ptr(inner), _ptr(junction), _stream(self.device)))
         return inner, junction
+
+    def run_traced(self, inner=None, junction=None):
+        """Run once with tracing; returns (inner, junction, clock, steps):
+        clock[p] = (start, end, workgroup) and steps[p, j] the clock after
+        sweep step j (the final product at j = N-1), in GPU shader cycles."""
+        if inner is None:
+            inner, junction = self.outputs()
+        n = self.n
+        clk = torch.zeros(35 * n, dtype=torch.int64, device=self.device)
+        _check(_lib.tt_batch_run_traced(self._h, _ptr(inner), _ptr(junction), _ptr(clk), _stream(self.device)))
+        c = clk.cpu()
+        per = torch.stack([c[0:2 * n:2], c[1:2 * n:2], c[2 * n:3 * n]], dim=1)
+        return inner, junction, per, c[3 * n:].view(n, 32)
 
     def junction(self, junction, p):
         x, y = self.pairs[p]

@@ -78,7 +78,8 @@ struct ttc_plan {
   int grid = 0;
   int lds_elems = 0;
   // level-by-level execution
-  int mode = 0;                // 0: persistent kernel, 1: one launch per level, 2: LDS-resident persistent kernel
+  int mode = 0;                // 0: persistent kernel, 1: one launch per level, 2: LDS-resident persistent
+                               // kernel, 3: the same with one interface buffer updated in place
   int buf_elems = 0;           // LDS-resident kernel: floats per interface buffer
   int levels = 0;              // max order - 1
   std::vector<int> lvl_off;    // item offsets per level (levels + 1 entries; level l at index l-1)
@@ -202,6 +203,7 @@ BatchArgs make_args(ttc_plan* P, const int* begin, const int* order, double* inn
   a.inner = inner;
   a.junction = junc;
   a.buf_elems = P->buf_elems;
+  a.npairs = P->n;
   (void)grid;
   return a;
 }
@@ -245,18 +247,19 @@ hipError_t run_persistent(ttc_plan* P, double* inner, float* junc, hipStream_t s
 
 hipError_t run_lds(ttc_plan* P, double* inner, float* junc, hipStream_t s) {
   BatchArgs a = make_args(P, P->d_begin, P->d_order, inner, junc, P->lds_elems, P->grid);
-  return launch_batch_lds(P->dt, a, P->grid, P->cfg.threads, s);
+  return launch_batch_lds(P->dt, a, P->grid, P->cfg.threads, P->mode == 3, s);
 }
 
 hipError_t run_mode(ttc_plan* P, double* inner, float* junc, hipStream_t s) {
   if (P->mode == 1) return run_levels(P, inner, junc, s);
-  if (P->mode == 2) return run_lds(P, inner, junc, s);
+  if (P->mode == 2 || P->mode == 3) return run_lds(P, inner, junc, s);
   return run_persistent(P, inner, junc, s);
 }
 
-// Largest number of LDS-resident workgroups per CU.
-int lds_kernel_per_cu(const ttc_plan* P) {
-  const int bytes = 2 * P->buf_elems * (int)sizeof(float) + 4 * 1024;
+// Largest number of LDS-resident workgroups per CU (bufs: interface buffers
+// per workgroup).
+int lds_kernel_per_cu(const ttc_plan* P, int bufs) {
+  const int bytes = bufs * P->buf_elems * (int)sizeof(float) + 4 * 1024;
   return std::max(1, std::min(2, (160 * 1024) / bytes));
 }
 
@@ -318,12 +321,13 @@ void cache_store(const std::string& key, const LaunchCfg& c) {
 
 ttc_status autotune(ttc_plan* P) {
   const std::string key = cache_key(P);
-  const char* forced = std::getenv("TTC_BATCH_MODE");  // testing: levels | persistent | lds
+  const char* forced = std::getenv("TTC_BATCH_MODE");  // testing: levels | persistent | lds | lds1
   int want = -1;
   if (forced) {
     if (std::strcmp(forced, "persistent") == 0) want = 0;
     if (std::strcmp(forced, "levels") == 0) want = 1;
     if (std::strcmp(forced, "lds") == 0) want = 2;
+    if (std::strcmp(forced, "lds1") == 0) want = 3;
   }
   LaunchCfg best;
   if (cache_lookup(key, &best) && (want < 0 || want == best.mode)) {
@@ -332,8 +336,10 @@ ttc_status autotune(ttc_plan* P) {
     return upload_assignment(P, best, &P->grid, &P->lds_elems);
   }
   std::vector<LaunchCfg> cands;
+  if (want < 0 || want == 3)
+    for (int pc = 1; pc <= lds_kernel_per_cu(P, 1); ++pc) cands.push_back({3, 256, pc});
   if (want < 0 || want == 2) {
-    for (int pc = 1; pc <= lds_kernel_per_cu(P); ++pc) {
+    for (int pc = 1; pc <= lds_kernel_per_cu(P, 2); ++pc) {
       cands.push_back({2, 256, pc});
       cands.push_back({2, 512, pc});
     }
@@ -653,6 +659,18 @@ ttc_status tt_batch_run(ttc_plan* P, double* d_inner, float* d_junction, void* s
   return TTC_OK;
 }
 
+ttc_status tt_batch_run_traced(ttc_plan* P, double* d_inner, float* d_junction, int64_t* d_clock, void* stream) {
+  if (!P) return fail(TTC_ERR_NULL, "plan is NULL");
+  if ((P->ops & TTC_OP_INNER) && !d_inner) return fail(TTC_ERR_NULL, "d_inner is NULL");
+  if ((P->ops & TTC_OP_SUFFIX2) && !d_junction) return fail(TTC_ERR_NULL, "d_junction is NULL");
+  if (!d_clock) return fail(TTC_ERR_NULL, "d_clock is NULL");
+  if (P->mode != 2 && P->mode != 3) return fail(TTC_ERR_UNSUPPORTED, "tracing needs an LDS-resident schedule");
+  BatchArgs a = make_args(P, P->d_begin, P->d_order, d_inner, d_junction, P->lds_elems, P->grid);
+  a.clock = reinterpret_cast<long long*>(d_clock);
+  TTC_HIP(launch_batch_lds(P->dt, a, P->grid, P->cfg.threads, P->mode == 3, (hipStream_t)stream));
+  return TTC_OK;
+}
+
 ttc_status tt_batch_run_plain(ttc_plan* P, double* d_inner, float* d_junction, void* stream) {
   if (!P) return fail(TTC_ERR_NULL, "plan is NULL");
   if ((P->ops & TTC_OP_INNER) && !d_inner) return fail(TTC_ERR_NULL, "d_inner is NULL");
@@ -661,7 +679,7 @@ ttc_status tt_batch_run_plain(ttc_plan* P, double* d_inner, float* d_junction, v
   // one launch per pair of the LDS-resident kernel (one workgroup each)
   for (int p = 0; p < P->n; ++p) {
     BatchArgs a = make_args(P, P->d_01, P->d_ident + p, d_inner, d_junction, 0, 1);
-    TTC_HIP(launch_batch_lds(P->dt, a, 1, 256, s));
+    TTC_HIP(launch_batch_lds(P->dt, a, 1, 256, false, s));
   }
   return TTC_OK;
 }

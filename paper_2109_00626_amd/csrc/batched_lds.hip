@@ -8,38 +8,47 @@
 // layout the next step reads), stores V_{N-2} (the junction of the
 // contraction over the last two positions) when asked, and finishes
 // <X, Y> = sum_i G_x^(0)[0, i, :] V_1 G_y^(0)[0, i, :]^T with an MFMA
-// product and an FP64 reduction.  Two interface buffers of `buf_elems`
-// floats each make up the dynamic LDS.
+// product and an FP64 reduction.  The dynamic LDS holds two interface
+// buffers of `buf_elems` floats used alternately, or (in-place variant) one
+// buffer that each step overwrites.
 #include "sweep_lds.hpp"
 #include "ttc_batch.h"
 #include "ttc_device.hpp"
 
 namespace ttc {
 
-template <typename Tin, int NT>
-__global__ __launch_bounds__(NT) void batch_lds_kernel(BatchArgs a) {
+// ONE: a single interface buffer updated in place (two workgroups per CU);
+// otherwise two buffers used alternately.
+template <typename Tin, int NT, bool ONE>
+__global__ __launch_bounds__(NT, ONE ? 2 : 1) void batch_lds_kernel(BatchArgs a) {
   constexpr int NW = NT / 64;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double red[16];
   __shared__ TTDev sx, sy;
   TTC_LDS float* const buf0 = (TTC_LDS float*)(smem);
-  TTC_LDS float* const buf1 = buf0 + a.buf_elems;
+  TTC_LDS float* const buf1 = ONE ? buf0 : buf0 + a.buf_elems;
   const int beg = a.wg_begin[blockIdx.x], end = a.wg_begin[blockIdx.x + 1];
   for (int w = beg; w < end; ++w) {
     const int p = a.order[w];
-    if (threadIdx.x == 0) {
+    if (a.clock && threadIdx.x == 0) {
+      a.clock[2 * p] = (long long)__builtin_readcyclecounter();
+      a.clock[2 * a.npairs + p] = blockIdx.x;
+    }
+    {
+      // descriptors, one entry per thread
       const PairDev pd = a.pairs[p];
-      sx.order = sy.order = pd.order;
       const int* ip = a.ipool + pd.ibase;
       const void* const* cp = a.ppool + pd.pbase;
-      for (int k = 0; k < pd.order; ++k) {
-        sx.modes[k] = sy.modes[k] = ip[k];
-        sx.cores[k] = cp[k];
-        sy.cores[k] = cp[pd.order + k];
+      const int e = threadIdx.x, N = pd.order;
+      if (e == 0) sx.order = sy.order = N;
+      if (e < N) {
+        sx.modes[e] = sy.modes[e] = ip[e];
+        sx.cores[e] = cp[e];
+        sy.cores[e] = cp[N + e];
       }
-      for (int k = 0; k <= pd.order; ++k) {
-        sx.ranks[k] = ip[pd.order + k];
-        sy.ranks[k] = ip[2 * pd.order + 1 + k];
+      if (e <= N) {
+        sx.ranks[e] = ip[N + e];
+        sy.ranks[e] = ip[2 * N + 1 + e];
       }
     }
     // V_N = [1], padded to a 16 x 16 block (pitch lds_pitch(1))
@@ -69,7 +78,8 @@ __global__ __launch_bounds__(NT) void batch_lds_kernel(BatchArgs a) {
         op.Nb = sy.ranks[k];
         op.Kb = sy.ranks[k + 1];
       }
-      lds_step<Tin, NW>(op, in, out, yf == yf_next);
+      if constexpr (ONE) lds_step_inplace<Tin, NW>(op, in, yf == yf_next);
+      else lds_step<Tin, NW>(op, in, out, yf == yf_next);
       if (k == N - 2 && (a.ops & TTC_OP_SUFFIX2)) {
         // V_{N-2} (R x P) in the layout chosen for the next step
         const int R = sx.ranks[k], P = sy.ranks[k];
@@ -84,6 +94,8 @@ __global__ __launch_bounds__(NT) void batch_lds_kernel(BatchArgs a) {
       in = out;
       out = t;
       yf = yf_next;
+      if (a.clock && threadIdx.x == 0)
+        a.clock[3L * a.npairs + 32L * p + (N - 1 - k)] = (long long)__builtin_readcyclecounter();
     }
     if (a.ops & TTC_OP_INNER) {
       double s = lds_final<Tin, NW>(sx.cores[0], sy.cores[0], sx.modes[0], sx.ranks[1], sy.ranks[1], in);
@@ -91,29 +103,47 @@ __global__ __launch_bounds__(NT) void batch_lds_kernel(BatchArgs a) {
       if (threadIdx.x == 0) a.inner[p] = s;
     }
     __syncthreads();
+    if (a.clock && threadIdx.x == 0) {
+      const long long t = (long long)__builtin_readcyclecounter();
+      a.clock[2 * p + 1] = t;
+      a.clock[3L * a.npairs + 32L * p + (N - 1)] = t;
+    }
   }
 }
 
 hipError_t batch_lds_set_lds(int bytes) {
-  const void* ks[] = {reinterpret_cast<const void*>(&batch_lds_kernel<float, 256>),
-                      reinterpret_cast<const void*>(&batch_lds_kernel<float, 512>),
-                      reinterpret_cast<const void*>(&batch_lds_kernel<bf16_t, 256>),
-                      reinterpret_cast<const void*>(&batch_lds_kernel<bf16_t, 512>)};
-  for (const void* k : ks) {
+  // bytes: two interface buffers; the in-place kernels take half
+  const void* two[] = {reinterpret_cast<const void*>(&batch_lds_kernel<float, 256, false>),
+                       reinterpret_cast<const void*>(&batch_lds_kernel<float, 512, false>),
+                       reinterpret_cast<const void*>(&batch_lds_kernel<bf16_t, 256, false>),
+                       reinterpret_cast<const void*>(&batch_lds_kernel<bf16_t, 512, false>)};
+  for (const void* k : two) {
     hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e != hipSuccess) return e;
+  }
+  const void* one[] = {reinterpret_cast<const void*>(&batch_lds_kernel<float, 256, true>),
+                       reinterpret_cast<const void*>(&batch_lds_kernel<bf16_t, 256, true>)};
+  for (const void* k : one) {
+    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes / 2);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
 }
 
-hipError_t launch_batch_lds(ttc_dtype dt, const BatchArgs& a, int grid, int threads, hipStream_t s) {
+hipError_t launch_batch_lds(ttc_dtype dt, const BatchArgs& a, int grid, int threads, bool inplace, hipStream_t s) {
+  if (inplace) {
+    const size_t lds = (size_t)a.buf_elems * sizeof(float);
+    if (dt == TTC_BF16) hipLaunchKernelGGL((batch_lds_kernel<bf16_t, 256, true>), dim3(grid), dim3(256), lds, s, a);
+    else hipLaunchKernelGGL((batch_lds_kernel<float, 256, true>), dim3(grid), dim3(256), lds, s, a);
+    return hipGetLastError();
+  }
   const size_t lds = (size_t)2 * a.buf_elems * sizeof(float);
   if (dt == TTC_BF16) {
-    if (threads <= 256) hipLaunchKernelGGL((batch_lds_kernel<bf16_t, 256>), dim3(grid), dim3(256), lds, s, a);
-    else hipLaunchKernelGGL((batch_lds_kernel<bf16_t, 512>), dim3(grid), dim3(512), lds, s, a);
+    if (threads <= 256) hipLaunchKernelGGL((batch_lds_kernel<bf16_t, 256, false>), dim3(grid), dim3(256), lds, s, a);
+    else hipLaunchKernelGGL((batch_lds_kernel<bf16_t, 512, false>), dim3(grid), dim3(512), lds, s, a);
   } else {
-    if (threads <= 256) hipLaunchKernelGGL((batch_lds_kernel<float, 256>), dim3(grid), dim3(256), lds, s, a);
-    else hipLaunchKernelGGL((batch_lds_kernel<float, 512>), dim3(grid), dim3(512), lds, s, a);
+    if (threads <= 256) hipLaunchKernelGGL((batch_lds_kernel<float, 256, false>), dim3(grid), dim3(256), lds, s, a);
+    else hipLaunchKernelGGL((batch_lds_kernel<float, 512, false>), dim3(grid), dim3(512), lds, s, a);
   }
   return hipGetLastError();
 }

@@ -328,6 +328,46 @@ __device__ __forceinline__ void lds_step(const StepOp& op, const TTC_LDS float* 
   }
 }
 
+// The same step with one LDS buffer: In is overwritten by Out.  Each wave
+// keeps at most two output tiles (two passes) in registers until every wave
+// has finished reading In, then the tiles are stored in the fixed order of
+// their mode-index parts.  Halving the LDS a pair needs lets two workgroups
+// share a compute unit, so one's step boundaries (drain, barriers, first
+// loads) overlap the other's MFMAs.  Ends with a workgroup barrier.
+template <typename Tin, int NW>
+__device__ __forceinline__ void lds_step_inplace(const StepOp& op, TTC_LDS float* Buf, bool native) {
+  const int RT = (op.Ma + 15) >> 4;  // <= 8 <= 2 NW
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  int S = 1, best = ((RT + NW - 1) / NW) * op.I;
+  for (int c = 2; c <= 2 * NW && c <= op.I && RT * c <= 2 * NW; c *= 2) {
+    const int cost = ((RT * c + NW - 1) / NW) * ((op.I + c - 1) / c);
+    if (cost < best) {
+      best = cost;
+      S = c;
+    }
+  }
+  const int items = RT * S;
+  f32x4 acc[SW_MAXT], keep[SW_MAXT];
+#pragma unroll 1
+  for (int it = 0; it < 2; ++it) {
+    const int item = w + it * NW;
+#pragma unroll
+    for (int t = 0; t < SW_MAXT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    if (item < items) lds_tile_v<Tin>(op, Buf, item % RT, item / RT, S, acc);
+    if (it == 0) {
+#pragma unroll
+      for (int t = 0; t < SW_MAXT; ++t) keep[t] = acc[t];
+    }
+  }
+  __syncthreads();  // In fully read
+  const int item0 = w, item1 = w + NW;
+  for (int ss = 0; ss < S; ++ss) {
+    if (item0 < items && item0 / RT == ss) lds_put(Buf, native, op.Ma, op.Nb, item0 % RT, keep, ss == 0);
+    if (item1 < items && item1 / RT == ss) lds_put(Buf, native, op.Ma, op.Nb, item1 % RT, acc, ss == 0);
+    __syncthreads();
+  }
+}
+
 // Per-thread part of <X, Y> = sum_i sum_p' T[i, p'] G_y^(0)[0, i, p'] with
 // T = G_x^(0)[0, :, :] . V_1 (an I x P1 product, K = R1) and V_1 stored
 // transposed in LDS (rows p', pitch lds_pitch(R1)); products and sums in FP64.

@@ -29,6 +29,8 @@ struct BatchArgs {
   double* inner;
   float* junction;
   int buf_elems;         // LDS-resident sweep: floats per interface buffer
+  long long* clock;      // tracing (may be null): start/end clock per pair, then the workgroup
+  int npairs;
 };
 
 // Level-by-level execution: one launch per step index from the right.
@@ -58,6 +60,6 @@ hipError_t launch_level(ttc_dtype dt, const LevelArgs& a, int nitems, size_t lds
 hipError_t launch_meet_level(ttc_dtype dt, const LevelArgs& a, int npairs, size_t lds, hipStream_t s);
 hipError_t launch_batch(ttc_dtype dt, const BatchArgs& a, int grid, int threads, hipStream_t s);
 hipError_t batch_lds_set_lds(int bytes);
-hipError_t launch_batch_lds(ttc_dtype dt, const BatchArgs& a, int grid, int threads, hipStream_t s);
+hipError_t launch_batch_lds(ttc_dtype dt, const BatchArgs& a, int grid, int threads, bool inplace, hipStream_t s);
 
 }  // namespace ttc

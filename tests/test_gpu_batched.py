@@ -36,7 +36,7 @@ def _check_pairs(plan, inner, junc, cores64, idx, tol):
     return worst
 
 
-@pytest.fixture(params=["lds", "levels", "persistent"])
+@pytest.fixture(params=["lds1", "lds", "levels", "persistent"])
 def batch_mode(request, monkeypatch):
     """Every batched schedule (the autotuner picks one by timing)."""
     monkeypatch.setenv("TTC_BATCH_MODE", request.param)
