@@ -272,6 +272,8 @@ def cpu_baseline(W, n_contr, budget_s=25.0):
 
 # ------------------------------------------------------------- main
 def main():
+    import numpy as np
+
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
@@ -416,6 +418,32 @@ def main():
             beside[f"layer4_{prec}_fwd_bwd_ms"] = round(a.elapsed_time(b) / 3, 4)
         beside["layer4_f32_fwd_bwd_ms"] = round(part_ms["layer4"], 4)
         beside["layer4_f32_fwd_ms"] = round(fwd_ms, 4)
+        # the core-by-core schedule (the method applied to the batch): one
+        # GEMM per core, 4x the FLOPs of the dense schedule on this shape
+        def cores(bwd):
+            Y = ttc.ttm_apply_dense(d["w"], d["X"], sched="cores")
+            if bwd:
+                _, dY = ttc.ttc_mse_loss(Y, d["T"])
+                ttc.ttm_apply_dense_bwd(d["w"], d["X"], dY, sched="cores")
+
+        for bwd, key in ((False, "layer4_cores_f32_fwd_ms"), (True, "layer4_cores_f32_fwd_bwd_ms")):
+            cores(bwd)
+            torch.cuda.synchronize()
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            cores(bwd)
+            b.record(stream)
+            torch.cuda.synchronize()
+            beside[key] = round(a.elapsed_time(b), 4)
+        # executed FLOPs: forward = sum over cores of 2 |P_k| |Q_k| (J_k R_k) (I_k R_{k+1})
+        sh = d["s"]
+        fl = 0.0
+        for k in range(4):
+            P = 8192 * int(np.prod(sh.cols[k + 1:])) if k < 3 else 8192
+            Q = int(np.prod(sh.modes[:k])) if k > 0 else 1
+            fl += 2.0 * P * Q * sh.cols[k] * sh.ranks[k] * sh.modes[k] * sh.ranks[k + 1]
+        beside["layer4_cores_f32_fwd_TFLOPs"] = round(fl / (beside["layer4_cores_f32_fwd_ms"] * 1e-3) / 1e12, 2)
 
     line = {
         "metric": "TT contractions/s + achieved GB/s or TFLOP/s vs roofline; fwd+bwd ms, plain vs batched",

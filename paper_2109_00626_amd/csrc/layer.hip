@@ -10,6 +10,16 @@
 // with the right environments Rt_{k-1} = Rt_k . W^(k)^T (Rt_{N-1} = dW).
 // Every contraction is the GEMM kernel below.
 //
+// Core-by-core schedule (the method applied to the batch): with X viewed as
+// Z_0[P_0, Q_0, J_0, R_0] (P_k = (b, j_{d-1}..j_{k+1}), Q_k = (i_{k-1}..i_0),
+// i_0 fastest), step k contracts (j_k, r_k) with the core:
+//   Z_{k+1}[(P_k, Q_k), (i_k, r_{k+1})] = Z_k[(P_k, Q_k), (j_k, r_k)] . Wp_k
+// with Wp_k[(j, r), (i, r1)] = G^(k)[r, i, j, r1].  The GEMM's store writes
+// each result straight into the layout the next step reads,
+// [P_{k+1}, (i_k, Q_k), j_{k+1}, r_{k+1}], and the last step into
+// Y[b, i_{d-1}..i_0].  The backward gathers each step's output gradient
+// through the same map, then dZ_k = dC_k Wp_k^T and dWp_k = Z_k^T dC_k.
+//
 // GEMM: 128 x 128 output tile per 256-thread workgroup, each wave a 64 x 64
 // quarter on 16x16 MFMA tiles (FP32: 16x16x4, BF16: 16x16x32 with FP32
 // accumulation), operands staged through double-buffered LDS.  Global
@@ -222,6 +232,34 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
   float* C = g.splits > 1 ? g.slab + (long)blockIdx.y * g.M * g.N : g.C;
   const long ldc = g.splits > 1 ? g.N : g.ldc;
   const float alpha = g.splits > 1 ? 1.f : g.alpha;
+  if (g.mapped) {
+    // relayout store: row and column parts of each address computed once
+    long roff[4][4], coff[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const long m = m0 + wm * 64 + 16 * i + 4 * lg + v;
+        const long q = m % g.map.mr0, t = m / g.map.mr0;
+        roff[i][v] = (t / g.map.mr1) * g.map.ms2 + (t % g.map.mr1) * g.map.ms1 + q * g.map.ms0;
+      }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const long n = n0 + wn * 64 + 16 * j + li;
+      coff[j] = (n / g.map.nr0) * g.map.ns1 + (n % g.map.nr0) * g.map.ns0;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int m = m0 + wm * 64 + 16 * i + 4 * lg + v;
+          const int n = n0 + wn * 64 + 16 * j + li;
+          if (m < g.M && n < g.N) g.C[roff[i][v] + coff[j]] = g.alpha * acc[i][j][v];
+        }
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -286,6 +324,47 @@ __global__ __launch_bounds__(256) void permute_kernel(PermArgs p) {
     src = row * p.cols + col;
   }
   p.dst[e] = p.src[src];
+}
+
+// dst[m * N + n] = src[map(m, n)], one thread per destination element.
+__global__ __launch_bounds__(256) void gather_mapped_kernel(GatherArgs a) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= a.M * a.N) return;
+  const long m = e / a.N, n = e - m * a.N;
+  const long q = m % a.map.mr0, t = m / a.map.mr0;
+  const long src = (t / a.map.mr1) * a.map.ms2 + (t % a.map.mr1) * a.map.ms1 + q * a.map.ms0 +
+                   (n / a.map.nr0) * a.map.ns1 + (n % a.map.nr0) * a.map.ns0;
+  a.dst[e] = a.src[src];
+}
+
+// Core G[r, i, j, r1] (R x I x J x R1) <-> Wp[(j, r), (i, r1)], one thread
+// per element of the destination.
+__global__ __launch_bounds__(256) void core_perm_kernel(const float* src, float* dst, int R, int I, int J, int R1,
+                                                        int dir) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long total = (long)R * I * J * R1;
+  if (e >= total) return;
+  if (dir == 0) {
+    // e indexes Wp: ((j * R + r) * I + i) * R1 + r1
+    long t = e;
+    const int r1 = (int)(t % R1);
+    t /= R1;
+    const int i = (int)(t % I);
+    t /= I;
+    const int r = (int)(t % R);
+    const int j = (int)(t / R);
+    dst[e] = src[(((long)r * I + i) * J + j) * R1 + r1];
+  } else {
+    // e indexes the core: ((r * I + i) * J + j) * R1 + r1
+    long t = e;
+    const int r1 = (int)(t % R1);
+    t /= R1;
+    const int j = (int)(t % J);
+    t /= J;
+    const int i = (int)(t % I);
+    const int r = (int)(t / I);
+    dst[e] = src[(((long)j * R + r) * I + i) * R1 + r1];
+  }
 }
 
 // Partial sums of (y - t)^2 per block and dy = scale * (y - t); the
@@ -363,6 +442,21 @@ hipError_t launch_gemm(bool a_kc, bool b_kc, bool bf16, const GemmArgs& g, hipSt
   const long MN = (long)g.M * g.N;
   hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)((MN + 255) / 256)), dim3(256), 0, s, g.slab, g.splits,
                      g.M, g.N, g.alpha, g.C, g.ldc);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather(const GatherArgs& a, hipStream_t s) {
+  const long n = a.M * a.N;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(gather_mapped_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_core_perm(const float* src, float* dst, int R, int I, int J, int R1, int dir, hipStream_t s) {
+  const long n = (long)R * I * J * R1;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(core_perm_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src, dst, R, I, J, R1,
+                     dir);
   return hipGetLastError();
 }
 

@@ -102,9 +102,13 @@ bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
 
 // One GEMM with split-K chosen to give the GPU enough workgroups.
 ttc_status gemm(bool a_kc, const float* A, long lda, bool b_kc, const float* B, long ldb, float* C, long ldc, int M,
-                int N, int K, bool bf16, float* slab, hipStream_t s) {
+                int N, int K, bool bf16, float* slab, hipStream_t s, const IdxMap* map = nullptr) {
   GemmArgs g;
   std::memset(&g, 0, sizeof(g));
+  if (map) {
+    g.mapped = true;
+    g.map = *map;
+  }
   g.M = M;
   g.N = N;
   g.K = K;
@@ -120,7 +124,7 @@ ttc_status gemm(bool a_kc, const float* A, long lda, bool b_kc, const float* B, 
   const long tiles = (long)((M + 127) / 128) * ((N + 127) / 128);
   const int bk = gemm_bk(bf16);
   int splits = 1;
-  if (tiles < 512) {
+  if (tiles < 512 && !map) {
     long want = (1024 + tiles - 1) / tiles;
     long by_k = K / (4L * bk);
     long by_slab = (long)(kSlabElems / ((size_t)M * N));
@@ -163,14 +167,167 @@ ttc_status build_dense(const ttc_ttm* m, LayerPlan& p, hipStream_t s) {
   return TTC_OK;
 }
 
-ttc_status check_common(const ttc_ttm* m, int64_t batch, ttc_prec prec, ttc_sched sched, bool* bf16) {
+// ------------------------------------------------- core-by-core schedule
+// Step k: Z_{k+1}[(P_k, Q_k), (i_k, r_{k+1})] = Z_k[(P_k, Q_k), (j_k, r_k)] . Wp_k
+// with |P_k| = batch * prod_{t>k} J_t, |Q_k| = prod_{t<k} I_t (see layer.hip).
+struct CoresPlan {
+  int d = 0;
+  std::vector<long> P, Q, K, N;  // per step
+  std::vector<float*> Wp;        // permuted cores
+  std::vector<float*> Z;         // Z_k, k = 1..d-1
+  float* dC = nullptr;           // backward buffers
+  float* dZ = nullptr;
+  float* dWp = nullptr;
+  float* slab = nullptr;
+};
+
+void cores_shape(const ttc_ttm* m, long batch, CoresPlan* p) {
+  const int d = m->order;
+  p->d = d;
+  p->P.assign(d, 0);
+  p->Q.assign(d, 0);
+  p->K.assign(d, 0);
+  p->N.assign(d, 0);
+  for (int k = 0; k < d; ++k) {
+    long P = batch, Q = 1;
+    for (int t = k + 1; t < d; ++t) P *= m->cols[t];
+    for (int t = 0; t < k; ++t) Q *= m->rows[t];
+    p->P[k] = P;
+    p->Q[k] = Q;
+    p->K[k] = (long)m->cols[k] * m->ranks[k];
+    p->N[k] = (long)m->rows[k] * m->ranks[k + 1];
+  }
+}
+
+double cores_flops(const CoresPlan& p) {
+  double f = 0;
+  for (int k = 0; k < p.d; ++k) f += 2.0 * p.P[k] * p.Q[k] * p.K[k] * p.N[k];
+  return f;
+}
+
+double dense_flops(const ttc_ttm* m, long batch) {
+  double rows = 1, cols = 1, chain = 0, pref = 1;
+  for (int k = 0; k < m->order; ++k) {
+    if (k > 0) chain += 2.0 * pref * m->ranks[k] * m->rows[k] * m->cols[k] * m->ranks[k + 1];
+    pref *= (double)m->rows[k] * m->cols[k];
+    rows *= m->rows[k];
+    cols *= m->cols[k];
+  }
+  return chain + 2.0 * batch * rows * cols;
+}
+
+void plan_cores(const ttc_ttm* m, long batch, bool backward, Arena& a, CoresPlan* p) {
+  cores_shape(m, batch, p);
+  const int d = p->d;
+  p->Wp.assign(d, nullptr);
+  for (int k = 0; k < d; ++k) p->Wp[k] = a.take((size_t)p->K[k] * p->N[k]);
+  p->Z.assign(d, nullptr);
+  long zmax = 1, cmax = 1, wmax = 1;
+  for (int k = 1; k < d; ++k) zmax = std::max(zmax, p->P[k] * p->Q[k] * p->K[k]);
+  for (int k = 0; k < d; ++k) {
+    cmax = std::max(cmax, p->P[k] * p->Q[k] * p->N[k]);
+    wmax = std::max(wmax, p->K[k] * p->N[k]);
+  }
+  if (backward) {
+    for (int k = 1; k < d; ++k) p->Z[k] = a.take((size_t)p->P[k] * p->Q[k] * p->K[k]);
+    p->dC = a.take((size_t)cmax);
+    p->dZ = a.take((size_t)zmax);
+    p->dWp = a.take((size_t)wmax);
+  } else if (d > 1) {
+    float* buf[2] = {a.take((size_t)zmax), d > 2 ? a.take((size_t)zmax) : nullptr};
+    for (int k = 1; k < d; ++k) p->Z[k] = buf[k & 1];
+  }
+  p->slab = a.take(kSlabElems);
+}
+
+// Store map of step k: its output (m = (p', j_{k+1}, q), n = (i_k, r_{k+1}))
+// into [P_{k+1}, (i_k, Q_k), j_{k+1}, r_{k+1}] (the last step: Y[b, i_k, Q_k]).
+IdxMap step_map(const ttc_ttm* m, const CoresPlan& p, int k) {
+  const long Jn = (k + 1 < p.d) ? m->cols[k + 1] : 1, Rn = m->ranks[k + 1], Q = p.Q[k];
+  IdxMap mp;
+  mp.mr0 = (int)Q;
+  mp.mr1 = (int)Jn;
+  mp.ms0 = Jn * Rn;
+  mp.ms1 = Rn;
+  mp.ms2 = (long)m->rows[k] * Q * Jn * Rn;
+  mp.nr0 = (int)Rn;
+  mp.ns0 = 1;
+  mp.ns1 = Q * Jn * Rn;
+  return mp;
+}
+
+// Forward steps; with Y null the last step is skipped (backward recompute).
+ttc_status cores_forward(const ttc_ttm* m, const CoresPlan& p, const float* X, float* Y, bool bf16, hipStream_t s) {
+  const int d = p.d;
+  for (int k = 0; k < d; ++k)
+    TTC_HIP(launch_core_perm(reinterpret_cast<const float*>(m->cores[k]), p.Wp[k], m->ranks[k], m->rows[k],
+                             m->cols[k], m->ranks[k + 1], 0, s));
+  const float* cur = X;
+  for (int k = 0; k < d; ++k) {
+    float* out = (k + 1 < d) ? p.Z[k + 1] : Y;
+    if (!out) break;
+    const IdxMap mp = step_map(m, p, k);
+    TTC_TRY(gemm(true, cur, p.K[k], false, p.Wp[k], p.N[k], out, 0, (int)(p.P[k] * p.Q[k]), (int)p.N[k],
+                 (int)p.K[k], bf16, p.slab, s, &mp));
+    cur = out;
+  }
+  return TTC_OK;
+}
+
+ttc_status cores_backward(const ttc_ttm* m, const CoresPlan& p, const float* X, const float* dY, float* dX,
+                          void* const* dcores, bool bf16, hipStream_t s) {
+  const int d = p.d;
+  TTC_TRY(cores_forward(m, p, X, nullptr, bf16, s));
+  const float* g = dY;  // gradient of step k's output, in its stored layout
+  for (int k = d - 1; k >= 0; --k) {
+    const long M = p.P[k] * p.Q[k];
+    GatherArgs ga;
+    ga.M = M;
+    ga.N = p.N[k];
+    ga.map = step_map(m, p, k);
+    ga.src = g;
+    ga.dst = p.dC;
+    TTC_HIP(launch_gather(ga, s));
+    if (dcores) {
+      // dWp_k = Z_k^T dC_k: A(m = (j, r), k = row) = Z_k[row * K + m], B(k = row, n) = dC[row * N + n]
+      const float* Zk = k == 0 ? X : p.Z[k];
+      TTC_TRY(gemm(false, Zk, p.K[k], false, p.dC, p.N[k], p.dWp, p.N[k], (int)p.K[k], (int)p.N[k], (int)M, bf16,
+                   p.slab, s));
+      TTC_HIP(launch_core_perm(p.dWp, reinterpret_cast<float*>(dcores[k]), m->ranks[k], m->rows[k], m->cols[k],
+                               m->ranks[k + 1], 1, s));
+    }
+    float* out = k > 0 ? p.dZ : dX;
+    if (out) {
+      // dZ_k = dC_k Wp_k^T: B(k = n_fwd, n = (j, r)) = Wp_k[(j, r) * N + n_fwd]
+      TTC_TRY(gemm(true, p.dC, p.N[k], true, p.Wp[k], p.N[k], out, p.K[k], (int)M, (int)p.K[k], (int)p.N[k], bf16,
+                   p.slab, s));
+    }
+    g = p.dZ;
+  }
+  return TTC_OK;
+}
+
+// Validates the call and resolves the schedule (AUTO: fewer FLOPs).
+ttc_status check_common(const ttc_ttm* m, int64_t batch, ttc_prec prec, ttc_sched sched, bool* bf16,
+                        bool* cores) {
   TTC_TRY(check_ttm(m));
   if (batch < 1 || batch > 2147483647LL) return fail(TTC_ERR_SHAPE, "batch outside [1, 2^31)");
   if (prec == TTC_PREC_BF16) *bf16 = true;
   else if (prec == TTC_PREC_AUTO || prec == TTC_PREC_F32) *bf16 = false;
   else return fail(TTC_ERR_UNSUPPORTED, "TT layer precision must be AUTO, F32 or BF16");
-  if (sched == TTC_SCHED_CORES) return fail(TTC_ERR_UNSUPPORTED, "core-by-core schedule not available");
-  if (sched != TTC_SCHED_AUTO && sched != TTC_SCHED_DENSE) return fail(TTC_ERR_UNSUPPORTED, "unknown schedule");
+  if (sched != TTC_SCHED_AUTO && sched != TTC_SCHED_DENSE && sched != TTC_SCHED_CORES)
+    return fail(TTC_ERR_UNSUPPORTED, "unknown schedule");
+  CoresPlan cp;
+  cores_shape(m, (long)batch, &cp);
+  bool cores_ok = true;
+  for (int k = 0; k < cp.d; ++k)
+    if ((double)cp.P[k] * cp.Q[k] * std::max(cp.K[k], cp.N[k]) >= 9.2e18 / 8 ||
+        (double)cp.P[k] * cp.Q[k] >= 2147483647.0)
+      cores_ok = false;
+  if (sched == TTC_SCHED_CORES && !cores_ok)
+    return fail(TTC_ERR_SHAPE, "core-by-core intermediates exceed 2^31 rows");
+  *cores = sched == TTC_SCHED_CORES ||
+           (sched == TTC_SCHED_AUTO && cores_ok && cores_flops(cp) < dense_flops(m, (long)batch));
   return TTC_OK;
 }
 
@@ -180,12 +337,17 @@ extern "C" {
 
 ttc_status ttm_apply_dense_query(const ttc_ttm* m, int64_t batch, ttc_prec prec, ttc_sched sched, int32_t backward,
                                  size_t* ws_bytes) {
-  bool bf16 = false;
-  TTC_TRY(check_common(m, batch, prec, sched, &bf16));
+  bool bf16 = false, cores = false;
+  TTC_TRY(check_common(m, batch, prec, sched, &bf16, &cores));
   if (!ws_bytes) return fail(TTC_ERR_NULL, "ws_bytes is NULL");
   Arena a(nullptr);
-  LayerPlan p;
-  plan_layer(m, backward != 0, a, &p);
+  if (cores) {
+    CoresPlan p;
+    plan_cores(m, (long)batch, backward != 0, a, &p);
+  } else {
+    LayerPlan p;
+    plan_layer(m, backward != 0, a, &p);
+  }
   *ws_bytes = a.off;
   return TTC_OK;
 }
@@ -197,9 +359,15 @@ ttc_status ttm_apply_dense(const ttc_ttm* m, const void* d_x, int64_t batch, voi
   if (!d_x || !d_y) return fail(TTC_ERR_NULL, "d_x or d_y is NULL");
   if (need > ws_bytes) return fail(TTC_ERR_WORKSPACE, "workspace smaller than ttm_apply_dense_query size");
   if (!d_ws) return fail(TTC_ERR_NULL, "d_ws is NULL");
-  bool bf16 = prec == TTC_PREC_BF16;
+  bool bf16 = false, cores = false;
+  TTC_TRY(check_common(m, batch, prec, sched, &bf16, &cores));
   hipStream_t s = (hipStream_t)stream;
   Arena a(d_ws);
+  if (cores) {
+    CoresPlan p;
+    plan_cores(m, (long)batch, false, a, &p);
+    return cores_forward(m, p, reinterpret_cast<const float*>(d_x), reinterpret_cast<float*>(d_y), bf16, s);
+  }
   LayerPlan p;
   plan_layer(m, false, a, &p);
   TTC_TRY(build_dense(m, p, s));
@@ -220,9 +388,16 @@ ttc_status ttm_apply_dense_bwd(const ttc_ttm* m, const void* d_x, const void* d_
   if (d_dcores)
     for (int k = 0; k < d; ++k)
       if (!d_dcores[k]) return fail(TTC_ERR_NULL, "NULL core-gradient buffer");
-  bool bf16 = prec == TTC_PREC_BF16;
+  bool bf16 = false, cores = false;
+  TTC_TRY(check_common(m, batch, prec, sched, &bf16, &cores));
   hipStream_t s = (hipStream_t)stream;
   Arena a(d_ws);
+  if (cores) {
+    CoresPlan p;
+    plan_cores(m, (long)batch, true, a, &p);
+    return cores_backward(m, p, reinterpret_cast<const float*>(d_x), reinterpret_cast<const float*>(d_dy),
+                          reinterpret_cast<float*>(d_dx), d_dcores, bf16, s);
+  }
   LayerPlan p;
   plan_layer(m, true, a, &p);
   TTC_TRY(build_dense(m, p, s));

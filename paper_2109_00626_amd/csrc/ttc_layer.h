@@ -6,6 +6,15 @@
 
 namespace ttc {
 
+// Index map of a mixed-radix relayout: element (m, n) of an M x N matrix
+// lives at
+//   (m / (mr0 mr1)) ms2 + ((m / mr0) % mr1) ms1 + (m % mr0) ms0
+//     + (n / nr0) ns1 + (n % nr0) ns0.
+struct IdxMap {
+  int mr0, mr1, nr0;
+  long ms0, ms1, ms2, ns0, ns1;
+};
+
 // C (M x N, row-major, ldc) = alpha * A . B with
 //   A(m, k) = a_kc ? A[m * lda + k] : A[k * lda + m]
 //   B(k, n) = b_kc ? B[n * ldb + k] : B[k * ldb + n]
@@ -21,6 +30,16 @@ struct GemmArgs {
   int splits;
   float* slab;
   bool vec_a, vec_b;  // 16-byte vector loads allowed
+  bool mapped;        // C element (m, n) goes to C[map(m, n)] (splits == 1)
+  IdxMap map;
+};
+
+// dst[m * N + n] = src[map(m, n)] (the inverse of a mapped GEMM store).
+struct GatherArgs {
+  long M, N;
+  IdxMap map;
+  const float* src;
+  float* dst;
 };
 
 struct PermArgs {
@@ -37,6 +56,10 @@ struct PermArgs {
 hipError_t launch_gemm(bool a_kc, bool b_kc, bool bf16, const GemmArgs& g, hipStream_t s);
 int gemm_bk(bool bf16);
 hipError_t launch_permute(const PermArgs& p, hipStream_t s);
+hipError_t launch_gather(const GatherArgs& a, hipStream_t s);
+// Core (R, I, J, R1) <-> its (J R) x (I R1) matrix Wp[(j, r), (i, r1)];
+// dir 0: core -> Wp, dir 1: Wp -> core.
+hipError_t launch_core_perm(const float* src, float* dst, int R, int I, int J, int R1, int dir, hipStream_t s);
 int mse_blocks(long n);
 hipError_t launch_mse(const float* y, const float* t, long n, float* dy, double* partials, double* out,
                       hipStream_t s);

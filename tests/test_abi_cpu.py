@@ -171,3 +171,25 @@ def test_grad_query(lib, abi):
     assert lib.tt_contract_inner_bwd_query(byref(x.s), byref(y.s), 1, byref(a)) == 0
     assert lib.tt_contract_inner_bwd_query(byref(x.s), byref(y.s), 4, byref(b)) == 0
     assert a.value > 0 and b.value > 0
+
+
+def test_layer_schedule_queries(lib, abi):
+    """Both layer schedules are accepted; AUTO takes the one with fewer FLOPs
+    (the dense one for the 4096 x 4096 order-4 layer); the core-by-core
+    backward keeps its three 8192 * 512 * 256 intermediates."""
+    s = C.layer4_shape()
+    rows = (c_int32 * 4)(*s.modes)
+    cols = (c_int32 * 4)(*s.cols)
+    rk = (c_int32 * 5)(*s.ranks)
+    cores = (c_void_p * 4)(*[FAKE] * 4)
+    m = abi.TTM(4, rows, cols, rk, 1, cores)
+    ws = {}
+    for name in ("auto", "dense", "cores"):
+        for bwd in (0, 1):
+            b = c_size_t(0)
+            assert lib.ttm_apply_dense_query(byref(m), 8192, abi.PREC["f32"], abi.SCHED[name], bwd, byref(b)) == 0
+            ws[name, bwd] = b.value
+    assert ws["auto", 0] == ws["dense", 0] and ws["auto", 1] == ws["dense", 1]
+    inter = 8192 * 512 * 8 * 32 * 4   # bytes of one intermediate
+    assert ws["cores", 1] >= 3 * inter + 2 * inter
+    assert 2 * inter <= ws["cores", 0] < 3 * inter

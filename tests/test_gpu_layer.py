@@ -20,8 +20,9 @@ def _upload(a):
     return torch.from_numpy(np.ascontiguousarray(a)).to(torch.float32).cuda()
 
 
+@pytest.mark.parametrize("sched", ["dense", "cores"])
 @pytest.mark.parametrize("prec", ["f32", "bf16"])
-def test_layer_fd_instance(ttc, prec):
+def test_layer_fd_instance(ttc, prec, sched):
     """Order 3, I = J = 4, ranks (1,4,4,1), batch 8: forward, loss and every
     gradient against the oracle's FP64 dense route (which itself is pinned by
     finite differences)."""
@@ -34,12 +35,12 @@ def test_layer_fd_instance(ttc, prec):
     Xs, Ts = to_np(Xg), to_np(Tg)
     ref = O.layer_forward_backward(ws, Xs, Ts) if prec == "f32" else O.layer_forward_backward(w, X, T)
     tol = TOL[prec]
-    Y = ttc.ttm_apply_dense(wg, Xg, prec=prec)
+    Y = ttc.ttm_apply_dense(wg, Xg, prec=prec, sched=sched)
     assert rel_fro(to_np(Y), ref["Y"]) <= tol
     L, dY = ttc.ttc_mse_loss(Y, Tg)
     assert abs(L.item() - ref["L"]) <= tol * ref["L"]
     assert rel_fro(to_np(dY), ref["dY"]) <= tol
-    dX, dG = ttc.ttm_apply_dense_bwd(wg, Xg, dY, prec=prec)
+    dX, dG = ttc.ttm_apply_dense_bwd(wg, Xg, dY, prec=prec, sched=sched)
     assert rel_fro(to_np(dX), ref["dX"]) <= tol
     assert max_core_rel([to_np(g) for g in dG], ref["dG"]) <= tol
 
@@ -100,6 +101,54 @@ def test_layer4_full_size(ttc):
     ref = O.layer_forward_backward(ws, to_np(Xs), to_np(Ts))
     assert rel_fro(to_np(dXs), ref["dX"]) <= TOL["f32"]
     assert max_core_rel([to_np(g) for g in dGs], ref["dG"]) <= TOL["f32"]
+
+
+@pytest.mark.parametrize("dims", [
+    ([4, 2, 3], [1, 3, 5, 1], [3, 4, 2], 37),       # rectangular, ragged batch
+    ([5], [1, 1], [7], 3),                          # order 1
+    ([3, 2, 2, 3], [1, 2, 6, 3, 1], [2, 3, 3, 2], 130),
+])
+def test_layer_cores_schedule(ttc, dims):
+    """The core-by-core schedule against the oracle: forward, dX and every
+    core gradient, on shapes with uneven modes, ranks and a ragged batch."""
+    rows, ranks, cols, B = dims
+    s = C.TTShape(rows, ranks, cols)
+    w = C.gen_tt_np(C.SEED_LAYER, 31, s)
+    ncol = int(np.prod(cols))
+    X = _batch(C.SEED_LAYER, 32, B, ncol)
+    T = _batch(C.SEED_LAYER, 33, B, int(np.prod(rows)))
+    wg, ws = to_gpu(w, "f32")
+    Xg, Tg = _upload(X), _upload(T)
+    ref = O.layer_forward_backward(ws, to_np(Xg), to_np(Tg))
+    Y = ttc.ttm_apply_dense(wg, Xg, sched="cores")
+    assert rel_fro(to_np(Y), ref["Y"]) <= TOL["f32"]
+    _, dY = ttc.ttc_mse_loss(Y, Tg)
+    dX, dG = ttc.ttm_apply_dense_bwd(wg, Xg, dY, sched="cores")
+    assert rel_fro(to_np(dX), ref["dX"]) <= TOL["f32"]
+    assert max_core_rel([to_np(g) for g in dG], ref["dG"]) <= TOL["f32"]
+
+
+def test_layer4_cores_full_size(ttc):
+    """The core-by-core schedule at the full 8192 x 4096 batch: forward and
+    dX against the dense schedule's results entrywise and against the oracle
+    on sampled rows; core gradients against the dense schedule's."""
+    import torch
+    s = C.layer4_shape()
+    w = C.gen_tt_np(C.SEED_LAYER, 1, s)
+    wg, ws = to_gpu(w, "f32")
+    Xg = C.gen_matrix_torch(C.SEED_LAYER, 2, 8192, 4096, "cuda", torch.float32)
+    Tg = C.gen_matrix_torch(C.SEED_LAYER, 3, 8192, 4096, "cuda", torch.float32)
+    Yc = ttc.ttm_apply_dense(wg, Xg, sched="cores")
+    Yd = ttc.ttm_apply_dense(wg, Xg, sched="dense")
+    assert float(torch.linalg.vector_norm(Yc - Yd) / torch.linalg.vector_norm(Yd)) <= TOL["f32"]
+    rows = np.random.RandomState(5).choice(8192, 32, replace=False)
+    assert rel_fro(to_np(Yc[rows]), to_np(Xg[rows]) @ O.mpo_full(ws).T) <= TOL["f32"]
+    _, dY = ttc.ttc_mse_loss(Yd, Tg)
+    dXc, dGc = ttc.ttm_apply_dense_bwd(wg, Xg, dY, sched="cores")
+    dXd, dGd = ttc.ttm_apply_dense_bwd(wg, Xg, dY, sched="dense")
+    assert float(torch.linalg.vector_norm(dXc - dXd) / torch.linalg.vector_norm(dXd)) <= TOL["f32"]
+    for a, b in zip(dGc, dGd):
+        assert float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b)) <= TOL["f32"]
 
 
 def test_layer4_bf16_forward(ttc):
