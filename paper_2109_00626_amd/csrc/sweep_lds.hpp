@@ -216,6 +216,7 @@ __device__ __forceinline__ void lds_tile(const StepOp& op, const TTC_LDS float* 
     for (int pt = 0; pt < PT; ++pt)
 #pragma unroll
       for (int v = 0; v < 4; ++v) acc[pt] = mfma4(st[v], gv[pt][v], acc[pt]);
+
     if (!more) break;
     // the prefetched operands become current (masked past the row ends)
     bool mb[4];
