@@ -201,8 +201,9 @@ __global__ __launch_bounds__(256) void grad_ckpt_kernel(GradArgs a) {
   }
 }
 
-// Phase B: block s recomputes the right interfaces of its segment from the
-// checkpoint, then walks left to right writing the gradient of every core.
+// Phase B: block s recomputes the interfaces of its segment from the
+// checkpoints: V_{k+1} right to left and W_k left to right, each stored in
+// slot k.
 template <typename Tin, typename Tc>
 __global__ __launch_bounds__(256) void grad_seg_kernel(GradArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -213,65 +214,74 @@ __global__ __launch_bounds__(256) void grad_seg_kernel(GradArgs a) {
   Tc* bufB = bufA + a.max_rp;
   Tc* lds_free = a.i_global ? reinterpret_cast<Tc*>(smem) : bufB + a.max_rp;
   Tc* T = a.t_global ? reinterpret_cast<Tc*>(a.t_global) + blockIdx.x * a.t_stride : lds_free;
-  Tc* segV = reinterpret_cast<Tc*>(a.segV) + (long)s * c * a.max_rp;  // slot k - k0 holds V_{k+1}
+  Tc* segV = reinterpret_cast<Tc*>(a.segV);
+  Tc* segW = reinterpret_cast<Tc*>(a.segW);
   const Tc* ckW = reinterpret_cast<const Tc*>(a.ckW) + (long)s * a.max_rp;
   const Tc* ckV = reinterpret_cast<const Tc*>(a.ckV) + (long)s * a.max_rp;
-  const Tc gz = (Tc)a.gz[0];
   // right interfaces V_{k1} .. V_{k0 + 1}
-  wg_copy<Tc>(segV + (long)(k1 - 1 - k0) * a.max_rp, ckV, a.x.ranks[k1] * a.y.ranks[k1]);
+  wg_copy<Tc>(segV + (long)(k1 - 1) * a.max_rp, ckV, a.x.ranks[k1] * a.y.ranks[k1]);
   __syncthreads();
   for (int k = k1 - 1; k > k0; --k) {
-    rl_step<Tin, Tc>(a.x, a.y, k, segV + (long)(k - k0) * a.max_rp, segV + (long)(k - 1 - k0) * a.max_rp, T,
-                     a.tcap);
+    rl_step<Tin, Tc>(a.x, a.y, k, segV + (long)k * a.max_rp, segV + (long)(k - 1) * a.max_rp, T, a.tcap);
   }
-  // left interface W_{k0}
+  // left interfaces W_{k0} .. W_{k1 - 1}
   wg_copy<Tc>(bufA, ckW, a.x.ranks[k0] * a.y.ranks[k0]);
   __syncthreads();
   Tc* cur = bufA;
   Tc* nxt = bufB;
   for (int k = k0; k < k1; ++k) {
-    const int Rp = a.x.ranks[k], Rn = a.x.ranks[k + 1];
-    const int Pp = a.y.ranks[k], Pn = a.y.ranks[k + 1];
-    const int I = a.x.modes[k];
-    const Tin* Gx = core_ptr<Tin>(a.x, k);
-    const Tin* Gy = core_ptr<Tin>(a.y, k);
-    const Tc* V = segV + (long)(k - k0) * a.max_rp;  // V_{k+1}: Rn x Pn
-    int ic = a.tcap / (Rp * Pn);
-    ic = ic < 1 ? 1 : (ic > I ? I : ic);
-    if (a.dx[k]) {
-      Tc* dX = reinterpret_cast<Tc*>(a.dx[k]);
-      for (int i0 = 0; i0 < I; i0 += ic) {
-        const int icn = (I - i0) < ic ? (I - i0) : ic;
-        // T[r'][(ii,p)] = W (Rp x Pp) . Gy[:, i0+ii, :]
-        wg_gemm<Tc, Tc, Tin, Tc>(Rp, icn * Pn, Pp, 1, 1, mv<Tc>(cur, Pp, 1), mv<Tin>(Gy + (long)i0 * Pn, I * Pn, 1),
-                                 ov<Tc>(T, icn * Pn, 1), false);
-        __syncthreads();
-        // dX[r'][i0+ii][r] = gz sum_p T[r'][ii][p] V[r][p]
-        wg_gemm<Tc, Tc, Tc, Tc>(Rp, Rn, Pn, icn, 1, mv<Tc>(T, icn * Pn, 1, 0, Pn), mv<Tc>(V, 1, Pn),
-                                ov<Tc>(dX + (long)i0 * Rn, I * Rn, 1, Rn), false, gz);
-        __syncthreads();
-      }
-    }
-    if (a.dy[k]) {
-      Tc* dY = reinterpret_cast<Tc*>(a.dy[k]);
-      for (int i0 = 0; i0 < I; i0 += ic) {
-        const int icn = (I - i0) < ic ? (I - i0) : ic;
-        // U[ii][r'][p] = Gx[r'][i0+ii][:] . V (Rn x Pn)
-        wg_gemm<Tc, Tin, Tc, Tc>(Rp, Pn, Rn, icn, 1, mv<Tin>(Gx + (long)i0 * Rn, I * Rn, 1, 0, Rn), mv<Tc>(V, Pn, 1),
-                                 ov<Tc>(T, Pn, 1, Rp * Pn), false);
-        __syncthreads();
-        // dY[p'][i0+ii][p] = gz sum_r' W[r'][p'] U[ii][r'][p]
-        wg_gemm<Tc, Tc, Tc, Tc>(Pp, Pn, Rp, icn, 1, mv<Tc>(cur, 1, Pp), mv<Tc>(T, Pn, 1, 0, Rp * Pn),
-                                ov<Tc>(dY + (long)i0 * Pn, I * Pn, 1, Pn), false, gz);
-        __syncthreads();
-      }
-    }
+    wg_copy<Tc>(segW + (long)k * a.max_rp, cur, a.x.ranks[k] * a.y.ranks[k]);
     if (k + 1 < k1) {
       lr_step<Tin, Tc>(a.x, a.y, k, cur, nxt, T, a.tcap);
       Tc* t = cur;
       cur = nxt;
       nxt = t;
     }
+    __syncthreads();
+  }
+}
+
+// Phase C: block (t, k, i) writes the gradient slice of core k at mode
+// index i (t = 0: X, t = 1: Y) from W_k and V_{k+1}:
+//   dX_k[:, i, :] = gz W_k G_y^(k)[:, i, :] V_{k+1}^T,
+//   dY_k[:, i, :] = gz W_k^T G_x^(k)[:, i, :] V_{k+1}.
+// Every slice is independent, so the whole gradient is one wide launch.
+template <typename Tin, typename Tc>
+__global__ __launch_bounds__(256) void grad_core_kernel(GradArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int N = a.x.order;
+  const int t = blockIdx.x & 1, rest = blockIdx.x >> 1;
+  const int k = rest % N, i = rest / N;
+  const int I = a.x.modes[k];
+  if (i >= I) return;
+  void* outp = t == 0 ? a.dx[k] : a.dy[k];
+  if (!outp) return;
+  const int Rp = a.x.ranks[k], Rn = a.x.ranks[k + 1];
+  const int Pp = a.y.ranks[k], Pn = a.y.ranks[k + 1];
+  const Tc* W = reinterpret_cast<const Tc*>(a.segW) + (long)k * a.max_rp;  // Rp x Pp
+  const Tc* V = reinterpret_cast<const Tc*>(a.segV) + (long)k * a.max_rp;  // Rn x Pn
+  Tc* T = a.g_global ? reinterpret_cast<Tc*>(a.g_global) + blockIdx.x * a.g_stride : reinterpret_cast<Tc*>(smem);
+  const Tc gz = (Tc)a.gz[0];
+  if (t == 0) {
+    const Tin* Gy = core_ptr<Tin>(a.y, k);
+    Tc* dX = reinterpret_cast<Tc*>(outp);
+    // T[r][p'] = sum_p W[r][p] G_y[p][i][p']
+    wg_gemm<Tc, Tc, Tin, Tc>(Rp, Pn, Pp, 1, 1, mv<Tc>(W, Pp, 1), mv<Tin>(Gy + (long)i * Pn, I * Pn, 1),
+                             ov<Tc>(T, Pn, 1), false);
+    __syncthreads();
+    // dX[r][i][r'] = gz sum_p' T[r][p'] V[r'][p']
+    wg_gemm<Tc, Tc, Tc, Tc>(Rp, Rn, Pn, 1, 1, mv<Tc>(T, Pn, 1), mv<Tc>(V, 1, Pn), ov<Tc>(dX + (long)i * Rn, I * Rn, 1),
+                            false, gz);
+  } else {
+    const Tin* Gx = core_ptr<Tin>(a.x, k);
+    Tc* dY = reinterpret_cast<Tc*>(outp);
+    // U[r][p'] = sum_r' G_x[r][i][r'] V[r'][p']
+    wg_gemm<Tc, Tin, Tc, Tc>(Rp, Pn, Rn, 1, 1, mv<Tin>(Gx + (long)i * Rn, I * Rn, 1), mv<Tc>(V, Pn, 1),
+                             ov<Tc>(T, Pn, 1), false);
+    __syncthreads();
+    // dY[p][i][p'] = gz sum_r W[r][p] U[r][p']
+    wg_gemm<Tc, Tc, Tc, Tc>(Pp, Pn, Rp, 1, 1, mv<Tc>(W, 1, Pp), mv<Tc>(T, Pn, 1), ov<Tc>(dY + (long)i * Pn, I * Pn, 1),
+                            false, gz);
   }
 }
 
@@ -282,6 +292,9 @@ static hipError_t set_lds(int bytes) {
                                      hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   if (e != hipSuccess) return e;
   e = hipFuncSetAttribute(reinterpret_cast<const void*>(&grad_ckpt_kernel<Tin, Tc>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute(reinterpret_cast<const void*>(&grad_core_kernel<Tin, Tc>),
                           hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   if (e != hipSuccess) return e;
   return hipFuncSetAttribute(reinterpret_cast<const void*>(&grad_seg_kernel<Tin, Tc>),
@@ -320,6 +333,15 @@ hipError_t launch_grad_ckpt(ttc_dtype dt, const GradArgs& a, size_t lds, hipStre
     case TTC_F64: hipLaunchKernelGGL((grad_ckpt_kernel<double, double>), dim3(2), dim3(256), lds, s, a); break;
     case TTC_F32: hipLaunchKernelGGL((grad_ckpt_kernel<float, float>), dim3(2), dim3(256), lds, s, a); break;
     default: hipLaunchKernelGGL((grad_ckpt_kernel<bf16_t, float>), dim3(2), dim3(256), lds, s, a); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_core(ttc_dtype dt, const GradArgs& a, int blocks, size_t lds, hipStream_t s) {
+  switch (dt) {
+    case TTC_F64: hipLaunchKernelGGL((grad_core_kernel<double, double>), dim3(blocks), dim3(256), lds, s, a); break;
+    case TTC_F32: hipLaunchKernelGGL((grad_core_kernel<float, float>), dim3(blocks), dim3(256), lds, s, a); break;
+    default: hipLaunchKernelGGL((grad_core_kernel<bf16_t, float>), dim3(blocks), dim3(256), lds, s, a); break;
   }
   return hipGetLastError();
 }

@@ -618,6 +618,34 @@ ttc_status ttm_apply(const ttc_ttm* m, const ttc_tt* v, ttc_prec prec, const ttc
   return TTC_OK;
 }
 
+}  // extern "C"
+
+namespace {
+// Launch shape of the per-slice gradient kernel: one block per (X or Y,
+// core, mode index) and a product buffer of max_k R_k x P_{k+1} elements,
+// in LDS when it fits.
+struct GradCoreShape {
+  int blocks;
+  long elems;
+  bool global;
+};
+GradCoreShape grad_core_shape(const ttc_tt* x, const ttc_tt* y, size_t cs) {
+  int imax = 1;
+  long e = 1;
+  for (int k = 0; k < x->order; ++k) {
+    imax = std::max(imax, x->modes[k]);
+    e = std::max(e, (long)x->ranks[k] * y->ranks[k + 1]);
+  }
+  GradCoreShape g;
+  g.blocks = 2 * x->order * imax;
+  g.elems = e;
+  g.global = (size_t)e * cs > (size_t)(lds_limit_bytes() - 1024);
+  return g;
+}
+}  // namespace
+
+extern "C" {
+
 ttc_status tt_contract_inner_bwd_query(const ttc_tt* x, const ttc_tt* y, int32_t ckpt_stride, size_t* ws_bytes) {
   TTC_TRY(check_pair(x, y));
   if (!ws_bytes) return fail(TTC_ERR_NULL, "ws_bytes is NULL");
@@ -631,8 +659,11 @@ ttc_status tt_contract_inner_bwd_query(const ttc_tt* x, const ttc_tt* y, int32_t
   a.take((size_t)ns * sz.max_rp * cs);
   a.take((size_t)ns * sz.max_rp * cs);
   a.take((size_t)ns * c * sz.max_rp * cs);
+  a.take((size_t)ns * c * sz.max_rp * cs);
   if (sz.t_global) a.take((size_t)std::max(ns, 2) * sz.t_block_bytes);
   if (sz.i_global) a.take((size_t)std::max(ns, 2) * sz.i_block_bytes);
+  const GradCoreShape gc = grad_core_shape(x, y, cs);
+  if (gc.global) a.take((size_t)gc.blocks * gc.elems * cs);
   *ws_bytes = a.off;
   return TTC_OK;
 }
@@ -666,10 +697,14 @@ ttc_status tt_contract_inner_bwd(const ttc_tt* x, const ttc_tt* y, const double*
   g.ckW = a.take((size_t)ns * sz.max_rp * cs);
   g.ckV = a.take((size_t)ns * sz.max_rp * cs);
   g.segV = a.take((size_t)ns * c * sz.max_rp * cs);
+  g.segW = a.take((size_t)ns * c * sz.max_rp * cs);
   g.t_global = sz.t_global ? a.take((size_t)std::max(ns, 2) * sz.t_block_bytes) : nullptr;
   g.t_stride = sz.tcap;
   g.i_global = sz.i_global ? a.take((size_t)std::max(ns, 2) * sz.i_block_bytes) : nullptr;
   g.i_stride = 2L * sz.max_rp;
+  const GradCoreShape gc = grad_core_shape(x, y, cs);
+  g.g_global = gc.global ? a.take((size_t)gc.blocks * gc.elems * cs) : nullptr;
+  g.g_stride = gc.elems;
   g.gz = d_gz;
   g.max_rp = sz.max_rp;
   g.tcap = sz.tcap;
@@ -680,6 +715,7 @@ ttc_status tt_contract_inner_bwd(const ttc_tt* x, const ttc_tt* y, const double*
   hipStream_t s = (hipStream_t)stream;
   TTC_HIP(launch_grad_ckpt(x->dtype, g, sz.lds, s));
   TTC_HIP(launch_grad_seg(x->dtype, g, sz.lds, s));
+  TTC_HIP(launch_grad_core(x->dtype, g, gc.blocks, gc.global ? 0 : (size_t)gc.elems * cs, s));
   return TTC_OK;
 }
 

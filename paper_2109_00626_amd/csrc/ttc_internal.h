@@ -42,7 +42,10 @@ struct GradArgs {
   int nseg;         // ceil(N / c)
   void* ckW;        // nseg x max_rp: W_{s c}
   void* ckV;        // nseg x max_rp: V_{min((s+1)c, N)}
-  void* segV;       // nseg x c x max_rp: V_{k+1} for k in segment s
+  void* segV;       // nseg x c x max_rp: V_{k+1} for k in segment s (slot k)
+  void* segW;       // nseg x c x max_rp: W_k for k in segment s (slot k)
+  void* g_global;   // per-block product buffers of the gradient kernel (null: LDS)
+  long g_stride;    // elements per block in g_global
   void* dx[TTC_MAX_ORDER];
   void* dy[TTC_MAX_ORDER];
   const double* gz;
@@ -113,6 +116,9 @@ hipError_t launch_sweep(ttc_dtype dt, const SweepArgs& a, int nblocks, size_t ld
 hipError_t launch_meet(ttc_dtype dt, const void* W, const void* V, int n, double* out, hipStream_t s);
 hipError_t launch_grad_ckpt(ttc_dtype dt, const GradArgs& a, size_t lds, hipStream_t s);
 hipError_t launch_grad_seg(ttc_dtype dt, const GradArgs& a, size_t lds, hipStream_t s);
+// One workgroup per (X or Y, core, mode index): the gradient slice from the
+// stored interfaces.  lds: bytes of its product buffer (0 with g_global).
+hipError_t launch_grad_core(ttc_dtype dt, const GradArgs& a, int blocks, size_t lds, hipStream_t s);
 hipError_t launch_lift(ttc_dtype dt, const LiftArgs& a, int total_lines, hipStream_t s);
 hipError_t launch_dense(bool f64, const DenseArgs& a, hipStream_t s);
 hipError_t launch_mode_n(ttc_dtype dt, const ModeNArgs& a, hipStream_t s);

@@ -117,3 +117,29 @@ def test_batch4096_sampled(ttc, dtype, batch_mode):
     plan.run(inner2, junc2)
     assert np.array_equal(to_np(inner2), inner_np)
     assert torch.equal(junc2, junc)
+
+
+def test_batch_traced_run(ttc):
+    """The traced launch gives the untraced results bit for bit; every pair
+    has an end clock after its start, its steps' clocks in between and in
+    order, and a workgroup inside the plan's grid."""
+    shapes = C.batch_pair_shapes(C.SEED_BATCH, 64)
+    gpu = []
+    for p, (sx, sy) in enumerate(shapes):
+        xg, _ = to_gpu(C.gen_tt_np(C.SEED_BATCH, 1 + 2 * p, sx), "f32")
+        yg, _ = to_gpu(C.gen_tt_np(C.SEED_BATCH, 2 + 2 * p, sy), "f32")
+        gpu.append((xg, yg))
+    plan = ttc.BatchPlan(gpu)
+    assert plan.config["mode"] in ("lds", "lds1", "persistent", "levels")
+    inner, junc = plan.run()
+    if plan.config["mode"] not in ("lds", "lds1"):
+        pytest.skip("tracing covers the LDS-resident schedules")
+    i2, j2, clk, steps = plan.run_traced()
+    import torch
+    assert torch.equal(i2, inner) and torch.equal(j2, junc)
+    clk, steps = clk.numpy(), steps.numpy()
+    assert np.all(clk[:, 1] > clk[:, 0])
+    assert np.all((clk[:, 2] >= 0) & (clk[:, 2] < 256 * plan.config["wg_per_cu"]))
+    for p, (sx, _) in enumerate(shapes):
+        s = steps[p, :sx.order]
+        assert s[0] >= clk[p, 0] and np.all(np.diff(s) >= 0) and s[-1] == clk[p, 1]
