@@ -332,10 +332,12 @@ class BatchPlan:
         o = self.junction_offsets[p]
         return junction[o:o + R * P].view(R, P)
 
-    def __del__(self):
+    def __del__(self, _destroy=_lib.tt_batch_plan_destroy):
+        # the destroy call is bound at definition time: at interpreter exit
+        # the module's globals may already be gone
         h = getattr(self, "_h", None)
         if h is not None and h.value:
-            _lib.tt_batch_plan_destroy(h)
+            _destroy(h)
             self._h = c_void_p(0)
 
 

@@ -70,6 +70,7 @@ struct ttc_plan {
   int* d_order = nullptr;
   int* d_ident = nullptr;   // 0..n-1 (per-pair launches)
   int* d_01 = nullptr;      // {0, 1}
+  int* d_claim = nullptr;   // LDS-resident kernels: work counter and exit count (zero between launches)
   float* d_iface = nullptr;
   float* d_tbuf = nullptr;
   int max_grid = 0;
@@ -143,19 +144,43 @@ double step_flops(const PairHost& p, int k) {
   return std::min(a, b);
 }
 
-// FLOPs the LDS-resident kernel executes on core k: tiles padded to 16, in
-// the order it picks.
 int pad16h(int n) { return (n + 15) & ~15; }
-double step_flops_exec(const PairHost& p, int k) {
-  const double I = p.modes[k];
-  const double Rp = pad16h(p.rx[k]), Rn = pad16h(p.rx[k + 1]), Pp = pad16h(p.ry[k]), Pn = pad16h(p.ry[k + 1]);
-  return 2 * I * std::min(Rp * Pn * (Rn + Pp), Pp * Rn * (Pn + Rp));
-}
 
 // Floats of one LDS interface buffer of the LDS-resident kernel for an
 // R x P interface, in either layout (rows padded to 16, pitch padded + 4).
 int lds_iface_elems_h(int R, int P) {
   return std::max(pad16h(P) * (pad16h(R) + 4), pad16h(R) * (pad16h(P) + 4));
+}
+
+// Time model of the LDS-resident kernel for one pair, in shader cycles of
+// one workgroup of four waves: per step a fixed cost (set-up, the first
+// loads' latency, barriers), a cost per loop iteration of the busiest wave
+// (the load latency one iteration of prefetch does not hide) and a cost
+// per MFMA of that wave; the constants are a least-squares fit to per-step
+// clocks of the 4096-pair workload.  Only used to order pairs (longest
+// first) and to balance the static assignment.
+double pair_time_model(const PairHost& h) {
+  const int NW = 4;
+  double t = 0;
+  for (int k = h.order - 1; k >= 1; --k) {
+    const int Rp = h.rx[k], Rn = h.rx[k + 1], Pp = h.ry[k], Pn = h.ry[k + 1], I = h.modes[k];
+    const long cx = (long)pad16h(Rp) * pad16h(Pn) * (pad16h(Rn) + pad16h(Pp));
+    const long cy = (long)pad16h(Pp) * pad16h(Rn) * (pad16h(Pn) + pad16h(Rp));
+    const bool yf = cy < cx;
+    const int Ma = yf ? Pp : Rp, Ka = yf ? Pn : Rn, Nb = yf ? Rp : Pp, Kb = yf ? Rn : Pn;
+    const int RT = (Ma + 15) / 16, KC = (Ka + 15) / 16, PT = (Nb + 15) / 16, QT = (Kb + 15) / 16;
+    int S = 1, best = ((RT + NW - 1) / NW) * I;
+    for (int c = 2; c <= 2 * NW && c <= I && RT * c <= 2 * NW; c *= 2) {
+      const int cost = ((RT * c + NW - 1) / NW) * ((I + c - 1) / c);
+      if (cost < best) {
+        best = cost;
+        S = c;
+      }
+    }
+    const double iters = (double)((RT * S + NW - 1) / NW) * ((I + S - 1) / S) * QT;
+    t += 22000.0 + 1625.0 * iters + 46.0 * iters * 4 * (KC + PT);
+  }
+  return t + 10000.0;
 }
 
 // Static longest-processing-time assignment: pairs sorted by cost, each
@@ -247,6 +272,7 @@ hipError_t run_persistent(ttc_plan* P, double* inner, float* junc, hipStream_t s
 
 hipError_t run_lds(ttc_plan* P, double* inner, float* junc, hipStream_t s) {
   BatchArgs a = make_args(P, P->d_begin, P->d_order, inner, junc, P->lds_elems, P->grid);
+  a.claim = P->d_claim;
   return launch_batch_lds(P->dt, a, P->grid, P->cfg.threads, P->mode == 3, s);
 }
 
@@ -267,6 +293,12 @@ ttc_status upload_assignment(ttc_plan* P, const LaunchCfg& c, int* grid_out, int
   const int grid = std::min(P->cus * c.per_cu, std::max(P->n, 1));
   std::vector<int> begin, order;
   lpt_assign(P->cost, grid, &begin, &order);
+  if (c.mode == 2 || c.mode == 3) {
+    // claimed one by one at run time: the whole list, longest first
+    order.resize(P->n);
+    for (int i = 0; i < P->n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return P->cost[a] > P->cost[b]; });
+  }
   TTC_HIP(hipMemcpy(P->d_begin, begin.data(), begin.size() * sizeof(int), hipMemcpyHostToDevice));
   TTC_HIP(hipMemcpy(P->d_order, order.data(), order.size() * sizeof(int), hipMemcpyHostToDevice));
   *grid_out = grid;
@@ -289,7 +321,7 @@ std::string cache_key(const ttc_plan* P) {
   mix(P->ops);
   mix(P->dt);
   std::ostringstream os;
-  os << "gfx950|abi" << TTC_ABI_VERSION << "|s3|" << std::hex << h;
+  os << "gfx950|abi" << TTC_ABI_VERSION << "|s4|" << std::hex << h;
   return os.str();
 }
 
@@ -444,20 +476,16 @@ ttc_status tt_batch_plan_create(const ttc_pair* pairs, int32_t n, uint32_t ops, 
     ppool.insert(ppool.end(), h.xc.begin(), h.xc.end());
     ppool.insert(ppool.end(), h.yc.begin(), h.yc.end());
     P->joff[i + 1] = P->joff[i] + ((ops & TTC_OP_SUFFIX2) ? (int64_t)h.rx[N - 2] * h.ry[N - 2] : 0);
-    double fl = 0, fl_exec = 0, by = 0;
-    for (int k = 1; k < N; ++k) {
-      fl += step_flops(h, k);
-      fl_exec += step_flops_exec(h, k);
-    }
+    double fl = 0, by = 0;
+    for (int k = 1; k < N; ++k) fl += step_flops(h, k);
     fl += 2.0 * h.modes[0] * h.rx[1] * h.ry[1] + 2.0 * h.rx[1] * h.ry[1];
-    fl_exec += 2.0 * h.modes[0] * h.rx[1] * h.ry[1];
     for (int k = 0; k < N; ++k)
       by += (double)esz * ((double)h.rx[k] * h.modes[k] * h.rx[k + 1] + (double)h.ry[k] * h.modes[k] * h.ry[k + 1]);
     by += (ops & TTC_OP_INNER) ? 8.0 : 0.0;
     by += 4.0 * (double)(P->joff[i + 1] - P->joff[i]);
     P->flops += fl;
     P->bytes += by;
-    P->cost[i] = fl_exec + 16.0 * by;  // FLOPs plus memory time at ~16 FLOP/byte
+    P->cost[i] = pair_time_model(h);
     for (int b = 1; b <= N; ++b) P->max_rp = std::max<long>(P->max_rp, (long)h.rx[b] * ((h.ry[b] & 1) ? h.ry[b] : h.ry[b] + 1));
     for (int b = 1; b <= N; ++b) P->buf_elems = std::max(P->buf_elems, lds_iface_elems_h(h.rx[b], h.ry[b]));
   }
@@ -485,6 +513,8 @@ ttc_status tt_batch_plan_create(const ttc_pair* pairs, int32_t n, uint32_t ops, 
   off += al(sizeof(int) * n);
   const size_t o_01 = off;
   off += al(sizeof(int) * 2);
+  const size_t o_claim = off;
+  off += al(sizeof(int) * 2);
   const size_t o_iface = off;
   off += al(sizeof(float) * 2 * P->max_rp * P->max_grid);
   const size_t o_tbuf = off;
@@ -502,11 +532,12 @@ ttc_status tt_batch_plan_create(const ttc_pair* pairs, int32_t n, uint32_t ops, 
   P->d_order = (int*)(base + o_order);
   P->d_ident = (int*)(base + o_ident);
   P->d_01 = (int*)(base + o_01);
+  P->d_claim = (int*)(base + o_claim);
   P->d_iface = (float*)(base + o_iface);
   P->d_tbuf = (float*)(base + o_tbuf);
   std::vector<int> ident(n);
   for (int i = 0; i < n; ++i) ident[i] = i;
-  const int zo[2] = {0, 1};
+  const int zo[2] = {0, 1}, zz[2] = {0, 0};
   ttc_status st = TTC_OK;
   auto cp = [&](void* dst, const void* src, size_t b) {
     if (st == TTC_OK && b) {
@@ -519,6 +550,7 @@ ttc_status tt_batch_plan_create(const ttc_pair* pairs, int32_t n, uint32_t ops, 
   cp(P->d_ppool, ppool.data(), sizeof(void*) * ppool.size());
   cp(P->d_ident, ident.data(), sizeof(int) * n);
   cp(P->d_01, zo, sizeof(zo));
+  cp(P->d_claim, zz, sizeof(zz));
   if (st == TTC_OK) {
     hipError_t ee = batch_set_lds(kLdsBytes);
     if (ee == hipSuccess) ee = batch_lds_set_lds(2 * P->buf_elems * (int)sizeof(float));
@@ -667,6 +699,7 @@ ttc_status tt_batch_run_traced(ttc_plan* P, double* d_inner, float* d_junction, 
   if (P->mode != 2 && P->mode != 3) return fail(TTC_ERR_UNSUPPORTED, "tracing needs an LDS-resident schedule");
   BatchArgs a = make_args(P, P->d_begin, P->d_order, d_inner, d_junction, P->lds_elems, P->grid);
   a.clock = reinterpret_cast<long long*>(d_clock);
+  a.claim = P->d_claim;
   TTC_HIP(launch_batch_lds(P->dt, a, P->grid, P->cfg.threads, P->mode == 3, (hipStream_t)stream));
   return TTC_OK;
 }

@@ -1,8 +1,13 @@
 // Batched interface sweeps with both interfaces of a pair held in LDS.
 //
-// Persistent launch: each workgroup owns a list of pairs fixed by the host
-// planner (longest first onto the least-loaded workgroup), no device-side
-// queue and no atomics.  For a pair of order N the workgroup sweeps right to
+// Persistent launch over a list of pairs sorted longest first.  Workgroups
+// claim the next list position from a counter in global memory when they
+// finish a pair (so the slowest pairs start first and no workgroup idles
+// while work remains), or, when no counter is given, each walks a fixed
+// slice of the list.  The counter is an agent-scope atomic (coherent across
+// the dies' L2 caches); the last workgroup to exit clears it, so every
+// launch (graph replays included) starts from zero.  Launches sharing one
+// counter must not overlap.  For a pair of order N the workgroup sweeps right to
 // left from V_N = [1] with the LDS-resident steps of sweep_lds.hpp (each
 // step in its cheaper contraction order, the interface written in the
 // layout the next step reads), stores V_{N-2} (the junction of the
@@ -27,8 +32,18 @@ __global__ __launch_bounds__(NT, ONE ? 2 : 1) void batch_lds_kernel(BatchArgs a)
   __shared__ TTDev sx, sy;
   TTC_LDS float* const buf0 = (TTC_LDS float*)(smem);
   TTC_LDS float* const buf1 = ONE ? buf0 : buf0 + a.buf_elems;
-  const int beg = a.wg_begin[blockIdx.x], end = a.wg_begin[blockIdx.x + 1];
-  for (int w = beg; w < end; ++w) {
+  __shared__ int claimed;
+  const bool dyn = a.claim != nullptr;
+  const int end = dyn ? a.npairs : a.wg_begin[blockIdx.x + 1];
+  for (int w = dyn ? 0 : a.wg_begin[blockIdx.x];; ++w) {
+    if (dyn) {
+      // every thread has read the previous value: the pair's body below
+      // passes several barriers before the next claim
+      if (threadIdx.x == 0) claimed = atomicAdd(a.claim, 1);
+      __syncthreads();
+      w = claimed;
+    }
+    if (w >= end) break;
     const int p = a.order[w];
     if (a.clock && threadIdx.x == 0) {
       a.clock[2 * p] = (long long)__builtin_readcyclecounter();
@@ -107,6 +122,14 @@ __global__ __launch_bounds__(NT, ONE ? 2 : 1) void batch_lds_kernel(BatchArgs a)
       const long long t = (long long)__builtin_readcyclecounter();
       a.clock[2 * p + 1] = t;
       a.clock[3L * a.npairs + 32L * p + (N - 1)] = t;
+    }
+  }
+  if (dyn && threadIdx.x == 0) {
+    // every claim of this workgroup precedes its exit count; the last one
+    // out finds no claims pending and clears both counters
+    if (atomicAdd(a.claim + 1, 1) == (int)gridDim.x - 1) {
+      atomicExch(a.claim, 0);
+      atomicExch(a.claim + 1, 0);
     }
   }
 }

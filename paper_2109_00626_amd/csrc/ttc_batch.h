@@ -31,6 +31,9 @@ struct BatchArgs {
   int buf_elems;         // LDS-resident sweep: floats per interface buffer
   long long* clock;      // tracing (may be null): start/end clock per pair, then the workgroup
   int npairs;
+  int* claim;            // LDS-resident kernels: when set, workgroups claim positions of `order`
+                         // (all npairs of them) from claim[0] and count exits in claim[1]; both are
+                         // zero at launch and the last workgroup to exit clears them
 };
 
 // Level-by-level execution: one launch per step index from the right.
