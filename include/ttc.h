@@ -242,7 +242,11 @@ ttc_status tt_contract_inner_bwd(const ttc_tt* x, const ttc_tt* y, const double*
  * descriptor (shapes and core pointers) when it is created; the core buffers
  * must stay alive and unchanged in place until the plan is destroyed.
  * tt_batch_plan_create synchronises the device once (descriptor upload and
- * tile selection).
+ * tile selection).  The LDS-resident schedules (modes 2 and 3 below) hand
+ * pairs to workgroups through a work counter owned by the plan, so runs of
+ * one plan (tt_batch_run, tt_batch_run_traced) must not overlap in time:
+ * issue them on one stream, or order them with events.  Different plans are
+ * independent.
  * ------------------------------------------------------------------------ */
 typedef struct {
   ttc_tt x;
