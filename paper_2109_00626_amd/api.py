@@ -4,6 +4,7 @@ current HIP stream.  It does no arithmetic of its own."""
 from __future__ import annotations
 
 import ctypes
+import sys
 from ctypes import POINTER, byref, c_double, c_int32, c_int64, c_size_t, c_void_p
 
 import torch
@@ -332,11 +333,11 @@ class BatchPlan:
         o = self.junction_offsets[p]
         return junction[o:o + R * P].view(R, P)
 
-    def __del__(self, _destroy=_lib.tt_batch_plan_destroy):
-        # the destroy call is bound at definition time: at interpreter exit
-        # the module's globals may already be gone
+    def __del__(self, _destroy=_lib.tt_batch_plan_destroy, _finalizing=sys.is_finalizing):
+        # at interpreter exit ctypes may already be torn down; the process
+        # ending releases the plan's device memory anyway
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
+        if h is not None and h.value and not _finalizing():
             _destroy(h)
             self._h = c_void_p(0)
 

@@ -134,17 +134,49 @@ __device__ __forceinline__ f32x4 mfma4(float a, float b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// Resource over elements [first, total) of a core when `valid`, else of zero
+// bytes (every load reads zero).  Branch-free, so that the resource stays in
+// scalar registers.
+__device__ __forceinline__ CoreRes core_rsrc_if(bool valid, const void* base, long first, long total, int esz) {
+  const uintptr_t a = reinterpret_cast<uintptr_t>(base) + (uintptr_t)(first * esz);
+  const uintptr_t a4 = a & ~(uintptr_t)3;
+  const int adj = (int)(a - a4);
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)a4);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(a4 >> 32));
+  const long span = (adj + (total - first) * esz + 3) & ~3L;
+  const int bytes = __builtin_amdgcn_readfirstlane(valid ? (int)span : 0);
+  char* p = reinterpret_cast<char*>(((uintptr_t)hi << 32) | lo);
+  CoreRes c;
+  c.r = __builtin_amdgcn_make_buffer_rsrc(p, (short)0, bytes, 0x00020000);
+  c.adj = __builtin_amdgcn_readfirstlane(adj);
+  return c;
+}
+
+// Mode indices a wave handles per loop trip for the tile counts KC, PT: small
+// tiles take several, so that each trip's MFMA work covers the latency of
+// the next trip's loads (issued at the trip's start and waited for at its
+// end), within the register budget of the largest tiles.
+template <int KC, int PT>
+struct TripWidth {
+  static constexpr int U = (KC + PT <= 4) ? 4 : (KC + PT <= 8) ? 2 : 1;
+};
+
 // Accumulate mode indices i = s0, s0 + S, ... into the a-tile `at` of Out
 // (its PT b-tiles, in acc).  KC = pad16(Ka) / 16, PT = pad16(Nb) / 16.
 // Values of core rows past Ka (resp. Kb) are the next entries of the core;
 // they meet zero padding of In, and are also masked to zero so that only
-// the operation's own elements reach the sums.
+// the operation's own elements reach the sums.  A loop trip covers U mode
+// indices i, i + S, ..., i + (U - 1) S (those past the core read zeros) and
+// one 16-wide slice qt of b'; the U stage-1 products share one read of the
+// In^T slice and form independent MFMA chains.  An index past I gets an
+// empty resource (its start may still lie inside the core, in another row).
 template <typename Tin, int KC, int PT>
 __device__ __forceinline__ void lds_tile(const StepOp& op, const TTC_LDS float* __restrict__ In, int at, int s0, int S,
                                          f32x4 (&acc)[SW_MAXT]) {
   typedef Raw4<Tin> R4;
   typedef typename R4::type raw_t;
   constexpr int esz = sizeof(Tin);
+  constexpr int U = TripWidth<KC, PT>::U;
   const int lane = threadIdx.x & 63, li = lane & 15, g = lane >> 4;
   const int I = op.I, Ka = op.Ka, Kb = op.Kb;
   const int QT = (Kb + 15) >> 4;
@@ -161,25 +193,32 @@ __device__ __forceinline__ void lds_tile(const StepOp& op, const TTC_LDS float* 
   for (int u = 0; u < 4; ++u) ma[u] = (KC - 1) * 16 + 4 * g + u < Ka;
   const TTC_LDS float* inl = In + li * ip + 4 * g;
   if (s0 >= I) return;
+  const int step = U * S;
 
   // current operands as FP32 (masked), next ones as loaded
-  f32x4 bx[KC], gv[PT];
-  raw_t bxn[KC], gvn[PT];
+  f32x4 bx[U][KC], gv[U][PT];
+  raw_t bxn[U][KC], gvn[U][PT];
   {
-    const CoreRes ra = core_rsrc(op.ga, (long)s0 * Ka, ta, esz);
-    const CoreRes rb = core_rsrc(op.gb, (long)s0 * Kb, tb, esz);
 #pragma unroll
-    for (int kc = 0; kc < KC; ++kc) bxn[kc] = R4::load(ra, aoff + kc * 16 * esz);
+    for (int u = 0; u < U; ++u) {
+      const CoreRes ra = core_rsrc_if(s0 + u * S < I, op.ga, (long)(s0 + u * S) * Ka, ta, esz);
+      const CoreRes rb = core_rsrc_if(s0 + u * S < I, op.gb, (long)(s0 + u * S) * Kb, tb, esz);
 #pragma unroll
-    for (int pt = 0; pt < PT; ++pt) gvn[pt] = R4::load(rb, boff[pt]);
+      for (int kc = 0; kc < KC; ++kc) bxn[u][kc] = R4::load(ra, aoff + kc * 16 * esz);
+#pragma unroll
+      for (int pt = 0; pt < PT; ++pt) gvn[u][pt] = R4::load(rb, boff[pt]);
+    }
     bool mb[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) mb[v] = 4 * g + v < Kb;
 #pragma unroll
-    for (int kc = 0; kc < KC - 1; ++kc) bx[kc] = R4::to_f32(bxn[kc]);
-    bx[KC - 1] = R4::to_f32(bxn[KC - 1], ma);
+    for (int u = 0; u < U; ++u) {
 #pragma unroll
-    for (int pt = 0; pt < PT; ++pt) gv[pt] = R4::to_f32(gvn[pt], mb);
+      for (int kc = 0; kc < KC - 1; ++kc) bx[u][kc] = R4::to_f32(bxn[u][kc]);
+      bx[u][KC - 1] = R4::to_f32(bxn[u][KC - 1], ma);
+#pragma unroll
+      for (int pt = 0; pt < PT; ++pt) gv[u][pt] = R4::to_f32(gvn[u][pt], mb);
+    }
     // all prologue loads done here, so no load issued before the loop is
     // still counted as pending inside it
     __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
@@ -189,33 +228,45 @@ __device__ __forceinline__ void lds_tile(const StepOp& op, const TTC_LDS float* 
     int ni = i, nq = qt + 1;
     if (nq == QT) {
       nq = 0;
-      ni = i + S;
+      ni = i + step;
     }
     const bool more = ni < I;
     if (more) {
       if (nq == 0) {
-        const CoreRes ra = core_rsrc(op.ga, (long)ni * Ka, ta, esz);
 #pragma unroll
-        for (int kc = 0; kc < KC; ++kc) bxn[kc] = R4::load(ra, aoff + kc * 16 * esz);
+        for (int u = 0; u < U; ++u) {
+          const CoreRes ra = core_rsrc_if(ni + u * S < I, op.ga, (long)(ni + u * S) * Ka, ta, esz);
+#pragma unroll
+          for (int kc = 0; kc < KC; ++kc) bxn[u][kc] = R4::load(ra, aoff + kc * 16 * esz);
+        }
       }
-      const CoreRes rb = core_rsrc(op.gb, (long)ni * Kb + nq * 16, tb, esz);
 #pragma unroll
-      for (int pt = 0; pt < PT; ++pt) gvn[pt] = R4::load(rb, boff[pt]);
+      for (int u = 0; u < U; ++u) {
+        const CoreRes rb = core_rsrc_if(ni + u * S < I, op.gb, (long)(ni + u * S) * Kb + nq * 16, tb, esz);
+#pragma unroll
+        for (int pt = 0; pt < PT; ++pt) gvn[u][pt] = R4::load(rb, boff[pt]);
+      }
     }
     // S_i^T rows qt*16.. (b') from In^T rows and the lane's G_A row
     f32x4 av[KC];
 #pragma unroll
     for (int kc = 0; kc < KC; ++kc) av[kc] = *reinterpret_cast<const TTC_LDS f32x4*>(inl + qt * 16 * ip + kc * 16);
-    f32x4 st = {0.f, 0.f, 0.f, 0.f};
+    f32x4 st[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) st[u] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int kc = 0; kc < KC; ++kc)
 #pragma unroll
-      for (int u = 0; u < 4; ++u) st = mfma4(av[kc][u], bx[kc][u], st);
+      for (int w = 0; w < 4; ++w)
+#pragma unroll
+        for (int u = 0; u < U; ++u) st[u] = mfma4(av[kc][w], bx[u][kc][w], st[u]);
     // Out[a-tile, b-tile pt] += S_i[:, qt-slice] . G_B[b-tile, i, qt-slice]^T
 #pragma unroll
-    for (int pt = 0; pt < PT; ++pt)
+    for (int u = 0; u < U; ++u)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) acc[pt] = mfma4(st[v], gv[pt][v], acc[pt]);
+      for (int pt = 0; pt < PT; ++pt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[pt] = mfma4(st[u][v], gv[u][pt][v], acc[pt]);
 
     if (!more) break;
     // the prefetched operands become current (masked past the row ends)
@@ -223,11 +274,14 @@ __device__ __forceinline__ void lds_tile(const StepOp& op, const TTC_LDS float* 
 #pragma unroll
     for (int v = 0; v < 4; ++v) mb[v] = nq * 16 + 4 * g + v < Kb;
 #pragma unroll
-    for (int pt = 0; pt < PT; ++pt) gv[pt] = R4::to_f32(gvn[pt], mb);
-    if (nq == 0) {
+    for (int u = 0; u < U; ++u) {
 #pragma unroll
-      for (int kc = 0; kc < KC - 1; ++kc) bx[kc] = R4::to_f32(bxn[kc]);
-      bx[KC - 1] = R4::to_f32(bxn[KC - 1], ma);
+      for (int pt = 0; pt < PT; ++pt) gv[u][pt] = R4::to_f32(gvn[u][pt], mb);
+      if (nq == 0) {
+#pragma unroll
+        for (int kc = 0; kc < KC - 1; ++kc) bx[u][kc] = R4::to_f32(bxn[u][kc]);
+        bx[u][KC - 1] = R4::to_f32(bxn[u][KC - 1], ma);
+      }
     }
     i = ni;
     qt = nq;
