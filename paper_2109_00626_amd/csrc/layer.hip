@@ -272,16 +272,27 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
       }
 }
 
-// C = alpha * sum over slabs, fixed order.
+// C = alpha * (sum over z of slab[z]): 32 consecutive elements per workgroup,
+// eight lanes per element, each lane summing every eighth partial in order,
+// then the eight sums added in lane order (a fixed order: deterministic).
 __global__ __launch_bounds__(256) void splitk_reduce_kernel(const float* slab, int splits, int M, int N, float alpha,
                                                             float* C, long ldc) {
-  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  __shared__ float part[8][33];
+  const int el = threadIdx.x & 31, zl = threadIdx.x >> 5;
   const long MN = (long)M * N;
-  if (e >= MN) return;
+  const long e = (long)blockIdx.x * 32 + el;
   float s = 0.f;
-  for (int z = 0; z < splits; ++z) s += slab[(long)z * MN + e];
-  const long m = e / N, n = e - m * N;
-  C[m * ldc + n] = alpha * s;
+  if (e < MN)
+    for (int z = zl; z < splits; z += 8) s += slab[(long)z * MN + e];
+  part[zl][el] = s;
+  __syncthreads();
+  if (zl == 0 && e < MN) {
+    float t = part[0][el];
+#pragma unroll
+    for (int q = 1; q < 8; ++q) t += part[q][el];
+    const long m = e / N, n = e - m * N;
+    C[m * ldc + n] = alpha * t;
+  }
 }
 
 // Pair-mode order (m_0 slowest, m_k = i_k * J_k + j_k) <-> W[i, j] with
@@ -324,6 +335,59 @@ __global__ __launch_bounds__(256) void permute_kernel(PermArgs p) {
     src = row * p.cols + col;
   }
   p.dst[e] = p.src[src];
+}
+
+// Tiled form of the same permutation (see TilePermArgs): the tile is read
+// with the source layout's contiguous digits fastest, transposed through
+// LDS (pitch Bp + 1: conflict-free both ways) and written with the
+// destination layout's contiguous digits fastest.
+__global__ __launch_bounds__(256) void tile_permute_kernel(TilePermArgs p) {
+  __shared__ float tile[kTilePermElems + 64];
+  __shared__ long offP[256];
+  const int Bp = p.Bp, Bm = p.Bm, pitch = Bp + 1, n = Bp * Bm;
+  // tile base offsets from the outer digits
+  long rem = blockIdx.x, baseP = 0, baseM = 0;
+  for (int q = 0; q < p.nout; ++q) {
+    const long dq = rem % p.orad[q];
+    rem /= p.orad[q];
+    baseP += dq * p.osP[q];
+    baseM += dq * p.osM[q];
+  }
+  // pair-mode offset of each combination c of the leading column digits
+  for (int c = threadIdx.x; c < Bm; c += 256) {
+    long r = c, o = 0;
+    for (int k = 0; k < p.t; ++k) {
+      o += (r % p.jrad[k]) * p.sPj[k];
+      r /= p.jrad[k];
+    }
+    offP[c] = o;
+  }
+  __syncthreads();
+  if (p.dir == 0) {
+    // pair-mode -> matrix: read runs of Bp, write runs of Bm
+    for (int e = threadIdx.x; e < n; e += 256) {
+      const int q = e % Bp, c = e / Bp;
+      tile[c * pitch + q] = p.src[baseP + offP[c] + q];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < n; e += 256) {
+      const int c = e % Bm, q = e / Bm;
+      const int il = q / p.Jl, jl = q - il * p.Jl;
+      p.dst[baseM + c + il * p.sMi + jl * p.sMj] = tile[c * pitch + q];
+    }
+  } else {
+    // matrix -> pair-mode: read runs of Bm, write runs of Bp
+    for (int e = threadIdx.x; e < n; e += 256) {
+      const int c = e % Bm, q = e / Bm;
+      const int il = q / p.Jl, jl = q - il * p.Jl;
+      tile[c * pitch + q] = p.src[baseM + c + il * p.sMi + jl * p.sMj];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < n; e += 256) {
+      const int q = e % Bp, c = e / Bp;
+      p.dst[baseP + offP[c] + q] = tile[c * pitch + q];
+    }
+  }
 }
 
 // dst[m * N + n] = src[map(m, n)], one thread per destination element.
@@ -440,7 +504,7 @@ hipError_t launch_gemm(bool a_kc, bool b_kc, bool bf16, const GemmArgs& g, hipSt
   }
   if (e != hipSuccess || g.splits <= 1) return e;
   const long MN = (long)g.M * g.N;
-  hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)((MN + 255) / 256)), dim3(256), 0, s, g.slab, g.splits,
+  hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)((MN + 31) / 32)), dim3(256), 0, s, g.slab, g.splits,
                      g.M, g.N, g.alpha, g.C, g.ldc);
   return hipGetLastError();
 }
@@ -457,6 +521,12 @@ hipError_t launch_core_perm(const float* src, float* dst, int R, int I, int J, i
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(core_perm_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src, dst, R, I, J, R1,
                      dir);
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_permute(const TilePermArgs& p, hipStream_t s) {
+  if (p.tiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(tile_permute_kernel, dim3((unsigned)p.tiles), dim3(256), 0, s, p);
   return hipGetLastError();
 }
 

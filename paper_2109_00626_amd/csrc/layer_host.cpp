@@ -125,7 +125,9 @@ ttc_status gemm(bool a_kc, const float* A, long lda, bool b_kc, const float* B, 
   const int bk = gemm_bk(bf16);
   int splits = 1;
   if (tiles < 512 && !map) {
-    long want = (1024 + tiles - 1) / tiles;
+    // about 1024 workgroups, at most 256 partial slabs (the reduction reads
+    // every slab once per output element)
+    long want = std::min(256L, (1024 + tiles - 1) / tiles);
     long by_k = K / (4L * bk);
     long by_slab = (long)(kSlabElems / ((size_t)M * N));
     splits = (int)std::max(1L, std::min(want, std::min(by_k, by_slab)));
@@ -133,6 +135,79 @@ ttc_status gemm(bool a_kc, const float* A, long lda, bool b_kc, const float* B, 
   g.splits = splits;
   g.slab = slab;
   TTC_HIP(launch_gemm(a_kc, b_kc, bf16, g, s));
+  return TTC_OK;
+}
+
+// The pair-mode <-> matrix permutation of an MPO's dense matrix: the tiled
+// kernel when a tile of at least two leading column digits fits in LDS,
+// else one thread per element.
+ttc_status permute_dense(const ttc_ttm* m, int dir, long cols, const float* src, float* dst, hipStream_t s) {
+  const int d = m->order;
+  std::vector<long> pstride(d), ri(d), cj(d);
+  pstride[d - 1] = 1;
+  for (int k = d - 2; k >= 0; --k) pstride[k] = pstride[k + 1] * m->rows[k + 1] * m->cols[k + 1];
+  ri[0] = cj[0] = 1;
+  for (int k = 1; k < d; ++k) {
+    ri[k] = ri[k - 1] * m->rows[k - 1];
+    cj[k] = cj[k - 1] * m->cols[k - 1];
+  }
+  long total = 1;
+  for (int k = 0; k < d; ++k) total *= (long)m->rows[k] * m->cols[k];
+  if (d >= 2) {
+    const int Bp = m->rows[d - 1] * m->cols[d - 1];
+    int t = 0, Bm = 1;
+    while (t < d - 1 && (long)Bm * m->cols[t] <= 256 && (long)Bm * m->cols[t] * (Bp + 1) <= kTilePermElems + 64) {
+      Bm *= m->cols[t];
+      ++t;
+    }
+    if (Bm >= 2) {
+      TilePermArgs tp;
+      std::memset(&tp, 0, sizeof(tp));
+      tp.dir = dir;
+      tp.Bp = Bp;
+      tp.Jl = m->cols[d - 1];
+      tp.sMi = ri[d - 1] * cols;
+      tp.sMj = cj[d - 1];
+      tp.t = t;
+      tp.Bm = Bm;
+      for (int k = 0; k < t; ++k) {
+        tp.jrad[k] = m->cols[k];
+        tp.sPj[k] = pstride[k];
+      }
+      // outer digits, the matrix's faster ones first: j_t .. j_{d-2}, i_0 .. i_{d-2}
+      int q = 0;
+      for (int k = t; k < d - 1; ++k, ++q) {
+        tp.orad[q] = m->cols[k];
+        tp.osP[q] = pstride[k];
+        tp.osM[q] = cj[k];
+      }
+      for (int k = 0; k < d - 1; ++k, ++q) {
+        tp.orad[q] = m->rows[k];
+        tp.osP[q] = (long)m->cols[k] * pstride[k];
+        tp.osM[q] = ri[k] * cols;
+      }
+      tp.nout = q;
+      tp.tiles = total / ((long)Bp * Bm);
+      tp.src = src;
+      tp.dst = dst;
+      TTC_HIP(launch_tile_permute(tp, s));
+      return TTC_OK;
+    }
+  }
+  PermArgs pa;
+  std::memset(&pa, 0, sizeof(pa));
+  pa.dir = dir;
+  pa.d = d;
+  for (int k = 0; k < d; ++k) {
+    pa.I[k] = m->rows[k];
+    pa.J[k] = m->cols[k];
+    pa.pstride[k] = pstride[k];
+  }
+  pa.cols = cols;
+  pa.total = total;
+  pa.src = src;
+  pa.dst = dst;
+  TTC_HIP(launch_permute(pa, s));
   return TTC_OK;
 }
 
@@ -149,22 +224,7 @@ ttc_status build_dense(const ttc_ttm* m, LayerPlan& p, hipStream_t s) {
                  (int)p.mprefix[k], (int)(Mk * R1), R, false, p.slab, s));
     cur = out;
   }
-  PermArgs pa;
-  std::memset(&pa, 0, sizeof(pa));
-  pa.dir = 0;
-  pa.d = d;
-  for (int k = 0; k < d; ++k) {
-    pa.I[k] = m->rows[k];
-    pa.J[k] = m->cols[k];
-  }
-  pa.pstride[d - 1] = 1;
-  for (int k = d - 2; k >= 0; --k) pa.pstride[k] = pa.pstride[k + 1] * m->rows[k + 1] * m->cols[k + 1];
-  pa.cols = p.cols;
-  pa.total = p.rows * p.cols;
-  pa.src = d == 1 ? reinterpret_cast<const float*>(m->cores[0]) : p.Dp;
-  pa.dst = p.Wd;
-  TTC_HIP(launch_permute(pa, s));
-  return TTC_OK;
+  return permute_dense(m, 0, p.cols, d == 1 ? reinterpret_cast<const float*>(m->cores[0]) : p.Dp, p.Wd, s);
 }
 
 // ------------------------------------------------- core-by-core schedule
@@ -235,7 +295,8 @@ void plan_cores(const ttc_ttm* m, long batch, bool backward, Arena& a, CoresPlan
     p->dWp = a.take((size_t)wmax);
   } else if (d > 1) {
     float* buf[2] = {a.take((size_t)zmax), d > 2 ? a.take((size_t)zmax) : nullptr};
-    for (int k = 1; k < d; ++k) p->Z[k] = buf[k & 1];
+    // Z_1, Z_2, ... alternate between the two buffers (one suffices for d = 2)
+    for (int k = 1; k < d; ++k) p->Z[k] = buf[(k - 1) & 1];
   }
   p->slab = a.take(kSlabElems);
 }
@@ -413,21 +474,7 @@ ttc_status ttm_apply_dense_bwd(const ttc_ttm* m, const void* d_x, const void* d_
   TTC_TRY(gemm(false, dY, p.rows, false, X, p.cols, p.Wd, p.cols, (int)p.rows, (int)p.cols, (int)batch, bf16,
                p.slab, s));
   // dW -> pair-mode order (the right environment of the last core)
-  PermArgs pa;
-  std::memset(&pa, 0, sizeof(pa));
-  pa.dir = 1;
-  pa.d = d;
-  for (int k = 0; k < d; ++k) {
-    pa.I[k] = m->rows[k];
-    pa.J[k] = m->cols[k];
-  }
-  pa.pstride[d - 1] = 1;
-  for (int k = d - 2; k >= 0; --k) pa.pstride[k] = pa.pstride[k + 1] * m->rows[k + 1] * m->cols[k + 1];
-  pa.cols = p.cols;
-  pa.total = p.rows * p.cols;
-  pa.src = p.Wd;
-  pa.dst = d == 1 ? reinterpret_cast<float*>(d_dcores[0]) : p.Dp;
-  TTC_HIP(launch_permute(pa, s));
+  TTC_TRY(permute_dense(m, 1, p.cols, p.Wd, d == 1 ? reinterpret_cast<float*>(d_dcores[0]) : p.Dp, s));
   const float* Rt = p.Dp;  // Rt_{d-1}: |m_<d-1| x (M_{d-1} R_d)
   for (int k = d - 1; k >= 1; --k) {
     const long Mk = (long)m->rows[k] * m->cols[k];

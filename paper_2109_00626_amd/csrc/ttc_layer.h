@@ -53,7 +53,31 @@ struct PermArgs {
   float* dst;
 };
 
+// The same permutation by tiles staged in LDS.  A tile spans the digits
+// that are contiguous in the pair-mode layout (i_{d-1}, j_{d-1}: Bp
+// elements) and the t leading column digits j_0 .. j_{t-1}, contiguous in
+// the matrix layout (Bm elements); both its read and its write are runs of
+// consecutive addresses.  The other digits (outer) enumerate the tiles.
+struct TilePermArgs {
+  int dir;                        // as PermArgs
+  int nout;                       // outer digits
+  int orad[2 * TTC_MAX_ORDER];    // their radices (first varies fastest)
+  long osP[2 * TTC_MAX_ORDER];    // their strides in the pair-mode layout
+  long osM[2 * TTC_MAX_ORDER];    // and in the matrix layout
+  int Bp, Jl;                     // I_{d-1} J_{d-1}, J_{d-1}
+  long sMi, sMj;                  // matrix strides of i_{d-1}, j_{d-1}
+  int t, Bm;                      // leading column digits, their product
+  int jrad[TTC_MAX_ORDER];        // J_0 .. J_{t-1}
+  long sPj[TTC_MAX_ORDER];        // their pair-mode strides
+  long tiles;
+  const float* src;
+  float* dst;
+};
+
 hipError_t launch_gemm(bool a_kc, bool b_kc, bool bf16, const GemmArgs& g, hipStream_t s);
+// Elements of the LDS tile of the tiled permutation (at most).
+constexpr int kTilePermElems = 8192;
+hipError_t launch_tile_permute(const TilePermArgs& p, hipStream_t s);
 int gemm_bk(bool bf16);
 hipError_t launch_permute(const PermArgs& p, hipStream_t s);
 hipError_t launch_gather(const GatherArgs& a, hipStream_t s);

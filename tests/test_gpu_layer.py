@@ -103,14 +103,16 @@ def test_layer4_full_size(ttc):
     assert max_core_rel([to_np(g) for g in dGs], ref["dG"]) <= TOL["f32"]
 
 
+@pytest.mark.parametrize("sched", ["cores", "dense"])
 @pytest.mark.parametrize("dims", [
     ([4, 2, 3], [1, 3, 5, 1], [3, 4, 2], 37),       # rectangular, ragged batch
     ([5], [1, 1], [7], 3),                          # order 1
     ([3, 2, 2, 3], [1, 2, 6, 3, 1], [2, 3, 3, 2], 130),
+    ([16, 3], [1, 5, 1], [40, 9], 21),              # wide last pair block, long leading column mode
 ])
-def test_layer_cores_schedule(ttc, dims):
-    """The core-by-core schedule against the oracle: forward, dX and every
-    core gradient, on shapes with uneven modes, ranks and a ragged batch."""
+def test_layer_cores_schedule(ttc, dims, sched):
+    """Both schedules against the oracle: forward, dX and every core
+    gradient, on shapes with uneven modes, ranks and a ragged batch."""
     rows, ranks, cols, B = dims
     s = C.TTShape(rows, ranks, cols)
     w = C.gen_tt_np(C.SEED_LAYER, 31, s)
@@ -120,10 +122,10 @@ def test_layer_cores_schedule(ttc, dims):
     wg, ws = to_gpu(w, "f32")
     Xg, Tg = _upload(X), _upload(T)
     ref = O.layer_forward_backward(ws, to_np(Xg), to_np(Tg))
-    Y = ttc.ttm_apply_dense(wg, Xg, sched="cores")
+    Y = ttc.ttm_apply_dense(wg, Xg, sched=sched)
     assert rel_fro(to_np(Y), ref["Y"]) <= TOL["f32"]
     _, dY = ttc.ttc_mse_loss(Y, Tg)
-    dX, dG = ttc.ttm_apply_dense_bwd(wg, Xg, dY, sched="cores")
+    dX, dG = ttc.ttm_apply_dense_bwd(wg, Xg, dY, sched=sched)
     assert rel_fro(to_np(dX), ref["dX"]) <= TOL["f32"]
     assert max_core_rel([to_np(g) for g in dG], ref["dG"]) <= TOL["f32"]
 
