@@ -53,6 +53,7 @@ def test_inner_pair10(ttc, dtype):
     ([3, 5, 2, 7, 4], [1, 3, 17, 5, 2, 1], [1, 9, 2, 33, 6, 1]),          # ragged ranks
     ([64, 4], [1, 70, 1], [1, 37, 1]),                                      # several tiles, ragged tail
     ([5], [1, 1], [1, 1]),                                                  # order 1
+    ([6, 9], [1, 7, 1], [1, 12, 1]),                                        # order 2
     ([16, 32, 8], [1, 128, 100, 1], [1, 90, 128, 1]),                       # large ranks
     ([2, 3, 2, 3, 2, 3, 2], [1, 2, 3, 4, 5, 4, 3, 1], [1, 1, 2, 1, 2, 1, 2, 1]),
 ])
@@ -120,6 +121,27 @@ def test_modes_ragged_prefix_suffix(ttc, modes, dtype):
     assert max_core_rel(nat, O.contract_natural(*ref, modes)) <= tol
     Z = to_np(ttc.tt_contract_modes(xg, yg, modes, "dense"))
     assert rel_fro(Z, O.contract_dense(*ref, modes)) <= tol
+
+
+@pytest.mark.parametrize("modes", [[0], [1], [0, 1]])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_modes_order2(ttc, modes, dtype):
+    """Order-2 pairs: a one-core prefix, a one-core suffix and both modes, in
+    the junction, natural and dense forms."""
+    x, y = random_pair(93, [5, 7], [1, 4, 1], [1, 6, 1])
+    xg, xs = to_gpu(x, dtype)
+    yg, ys = to_gpu(y, dtype)
+    tol = TOL[dtype]
+    if modes != [0, 1]:
+        K = to_np(ttc.tt_contract_modes(xg, yg, modes, "junction"))
+        assert rel_fro(K, O.contract_junction(xs, ys, modes)[2]) <= tol
+    nat = ttc.tt_contract_modes(xg, yg, modes, "natural")
+    if modes == [0, 1]:
+        assert scalar_err(nat.item(), O.inner_lr(xs, ys), tt_norm(xs), tt_norm(ys)) <= tol
+    else:
+        assert max_core_rel([to_np(t) for t in nat], O.contract_natural(xs, ys, modes)) <= tol
+        Z = to_np(ttc.tt_contract_modes(xg, yg, modes, "dense"))
+        assert rel_fro(Z, O.contract_dense(xs, ys, modes)) <= tol
 
 
 def test_modes_pair10_prefix5(ttc):
@@ -224,6 +246,19 @@ def test_mpo_small_dtypes(ttc):
     assert all(torch.equal(a, b) for a, b in zip(out, vg))
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+def test_mpo_orders_1_2(ttc, dtype):
+    for sw, sv in ((C.TTShape([6], [1, 1], [5]), C.TTShape([5], [1, 1])),
+                   (C.TTShape([3, 4], [1, 7, 1], [5, 2]), C.TTShape([5, 2], [1, 3, 1]))):
+        w = C.gen_tt_np(47, 1, sw)
+        v = C.gen_tt_np(47, 2, sv)
+        wg, ws = to_gpu(w, dtype)
+        vg, vs = to_gpu(v, dtype)
+        out = [to_np(t) for t in ttc.ttm_apply(wg, vg)]
+        want = O.mpo_tt(ws, vs) if dtype != "bf16" else O.mpo_tt(w, v)
+        assert max_core_rel(out, want) <= TOL[dtype], (sw.order, dtype)
+
+
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
 def test_mpo_tiles_and_tails(ttc, dtype):
     """Several MFMA tiles along a' and r', K chunks with a ragged tail (J = 40,
@@ -277,6 +312,24 @@ def test_inner_grad(ttc, dtype, stride):
     yg, ys = to_gpu(y, dtype)
     gx, gy = ttc.tt_contract_inner_bwd(xg, yg, 0.75, ckpt_stride=stride)
     wx, wy = O.inner_grad(xs, ys, 0.75)
+    assert max_core_rel([to_np(t) for t in gx], wx) <= TOL[dtype]
+    assert max_core_rel([to_np(t) for t in gy], wy) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("case", [
+    ([5], [1, 1], [1, 1]),                                  # order 1
+    ([4, 6], [1, 3, 1], [1, 5, 1]),                         # order 2
+    ([2, 3, 2], [1, 160, 150, 1], [1, 150, 160, 1]),       # slices too large for LDS (FP64)
+    ([2, 2, 2], [1, 210, 200, 1], [1, 200, 210, 1]),       # and for FP32
+])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_inner_grad_shapes(ttc, case, dtype):
+    modes, rx, ry = case
+    x, y = random_pair(57, modes, rx, ry)
+    xg, xs = to_gpu(x, dtype)
+    yg, ys = to_gpu(y, dtype)
+    gx, gy = ttc.tt_contract_inner_bwd(xg, yg, -1.5)
+    wx, wy = O.inner_grad(xs, ys, -1.5)
     assert max_core_rel([to_np(t) for t in gx], wx) <= TOL[dtype]
     assert max_core_rel([to_np(t) for t in gy], wy) <= TOL[dtype]
 
