@@ -31,6 +31,7 @@ FLAGS = [
 # operand buffer is live.
 EXTRA = {
     "batched_lds.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+    "pair_lds.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
 }
 
 

@@ -229,10 +229,65 @@ void natural_shape(const ttc_tt* x, const ttc_tt* y, BlockKind kind, int k, std:
   }
 }
 
+// Reversed, rank-transposed copies of cores [0, n) of X and Y in the
+// workspace (core j of the copy is core n-1-j with its rank axes exchanged)
+// and their descriptors: the right-to-left sweep of the copy is the
+// left-to-right sweep of the original.  With a null arena base only sizes.
+void reversed_pair(const ttc_tt* x, const ttc_tt* y, int n, Arena& ws, TTDev* xr, TTDev* yr, CoreRevArgs* ra) {
+  const size_t esz = x->dtype == TTC_BF16 ? 2 : 4;
+  std::memset(xr, 0, sizeof(*xr));
+  std::memset(yr, 0, sizeof(*yr));
+  std::memset(ra, 0, sizeof(*ra));
+  xr->order = yr->order = n;
+  ra->esz = (int)esz;
+  const ttc_tt* t[2] = {x, y};
+  TTDev* d[2] = {xr, yr};
+  for (int q = 0; q < 2; ++q) {
+    for (int j = 0; j < n; ++j) {
+      const int m = n - 1 - j;
+      const int R = t[q]->ranks[m], I = t[q]->modes[m], R1 = t[q]->ranks[m + 1];
+      void* dst = ws.take((size_t)R * I * R1 * esz);
+      d[q]->modes[j] = I;
+      d[q]->cores[j] = dst;
+      CoreRevItem& c = ra->c[ra->n++];
+      c.src = t[q]->cores[m];
+      c.dst = dst;
+      c.R = R;
+      c.I = I;
+      c.R1 = R1;
+    }
+    for (int j = 0; j <= n; ++j) d[q]->ranks[j] = t[q]->ranks[n - j];
+  }
+}
+
+bool lds_path(const ttc_tt* x, const ttc_tt* y) {
+  return x->dtype != TTC_F64 && pair_lds_ok(to_dev(x), to_dev(y));
+}
+
 // Runs the junction sweep (prefix: W_k left to right; suffix: V_k right to left)
 // into `kout` (compute type).
 ttc_status run_junction(const ttc_tt* x, const ttc_tt* y, BlockKind kind, int k, void* kout, Arena& ws,
                         size_t ws_bytes, bool sizing, hipStream_t s) {
+  if (lds_path(x, y)) {
+    // one workgroup, interface in LDS; a prefix runs on the reversed block
+    PairLdsArgs pa;
+    std::memset(&pa, 0, sizeof(pa));
+    CoreRevArgs ra;
+    if (kind == BK_PREFIX) {
+      reversed_pair(x, y, k, ws, &pa.side[0].x, &pa.side[0].y, &ra);
+      pa.side[0].stop = 0;
+    } else {
+      pa.side[0].x = to_dev(x);
+      pa.side[0].y = to_dev(y);
+      pa.side[0].stop = k;
+    }
+    if (sizing) return TTC_OK;
+    if (ws.off > ws_bytes) return fail(TTC_ERR_WORKSPACE, "workspace too small");
+    pa.side[0].out = reinterpret_cast<float*>(kout);
+    if (kind == BK_PREFIX) TTC_HIP(launch_core_reverse(ra, s));
+    TTC_HIP(launch_pair_lds(x->dtype, pa, 1, s));
+    return TTC_OK;
+  }
   SweepSizing sz;
   const int k0 = kind == BK_PREFIX ? 0 : k, k1 = kind == BK_PREFIX ? k : x->order;
   TTC_TRY(size_sweep(x, y, k0, k1, &sz));
@@ -262,6 +317,18 @@ ttc_status run_junction(const ttc_tt* x, const ttc_tt* y, BlockKind kind, int k,
 // Bidirectional inner product meeting at bond N/2.
 ttc_status run_inner(const ttc_tt* x, const ttc_tt* y, double* d_out, Arena& ws, size_t ws_bytes, bool sizing,
                      hipStream_t s) {
+  if (lds_path(x, y)) {
+    // one right-to-left sweep with the interface in LDS, then the first cores
+    if (sizing) return TTC_OK;
+    PairLdsArgs pa;
+    std::memset(&pa, 0, sizeof(pa));
+    pa.side[0].x = to_dev(x);
+    pa.side[0].y = to_dev(y);
+    pa.side[0].stop = 1;
+    pa.side[0].inner = d_out;
+    TTC_HIP(launch_pair_lds(x->dtype, pa, 1, s));
+    return TTC_OK;
+  }
   const int N = x->order, c = N / 2;
   const size_t cs = comp_size(x->dtype);
   const size_t rp = (size_t)x->ranks[c] * y->ranks[c];
@@ -642,6 +709,30 @@ GradCoreShape grad_core_shape(const ttc_tt* x, const ttc_tt* y, size_t cs) {
   g.global = (size_t)e * cs > (size_t)(lds_limit_bytes() - 1024);
   return g;
 }
+
+// Buffers of the gradient's LDS-sweep path: every V_{k+1} and W_k stored
+// (slot k of segV / segW, R x P row-major FP32), the reversed pair for the
+// left-to-right sweep, and the product buffers of the slice kernel.
+struct GradLds {
+  int max_rp = 1;
+  float* segV = nullptr;
+  float* segW = nullptr;
+  TTDev xr, yr;
+  CoreRevArgs ra;
+  GradCoreShape gc;
+  void* g_global = nullptr;
+};
+void grad_lds_take(const ttc_tt* x, const ttc_tt* y, Arena& a, GradLds* g) {
+  const int N = x->order;
+  long m = 1;
+  for (int b = 0; b <= N; ++b) m = std::max(m, (long)x->ranks[b] * y->ranks[b]);
+  g->max_rp = (int)m;
+  g->segV = reinterpret_cast<float*>(a.take((size_t)N * m * sizeof(float)));
+  g->segW = reinterpret_cast<float*>(a.take((size_t)N * m * sizeof(float)));
+  reversed_pair(x, y, N, a, &g->xr, &g->yr, &g->ra);
+  g->gc = grad_core_shape(x, y, sizeof(float));
+  g->g_global = g->gc.global ? a.take((size_t)g->gc.blocks * g->gc.elems * sizeof(float)) : nullptr;
+}
 }  // namespace
 
 extern "C" {
@@ -649,6 +740,13 @@ extern "C" {
 ttc_status tt_contract_inner_bwd_query(const ttc_tt* x, const ttc_tt* y, int32_t ckpt_stride, size_t* ws_bytes) {
   TTC_TRY(check_pair(x, y));
   if (!ws_bytes) return fail(TTC_ERR_NULL, "ws_bytes is NULL");
+  if (lds_path(x, y)) {
+    Arena a(nullptr);
+    GradLds g;
+    grad_lds_take(x, y, a, &g);
+    *ws_bytes = a.off;
+    return TTC_OK;
+  }
   const int N = x->order;
   const int c = ckpt_stride > 0 ? std::min<int>(ckpt_stride, N) : default_stride(N);
   const int ns = (N + c - 1) / c;
@@ -682,6 +780,48 @@ ttc_status tt_contract_inner_bwd(const ttc_tt* x, const ttc_tt* y, const double*
     if (d_dy && !d_dy[k]) return fail(TTC_ERR_NULL, "NULL gradient buffer in d_dy");
   }
   TTC_TRY(ensure_init());
+  hipStream_t s = (hipStream_t)stream;
+  if (lds_path(x, y)) {
+    // two workgroups store every interface (V right to left, W as the
+    // reversed pair's V), then one wide launch forms every slice
+    Arena a(d_ws);
+    GradLds gl;
+    grad_lds_take(x, y, a, &gl);
+    TTC_HIP(launch_core_reverse(gl.ra, s));
+    PairLdsArgs pa;
+    std::memset(&pa, 0, sizeof(pa));
+    pa.side[0].x = to_dev(x);
+    pa.side[0].y = to_dev(y);
+    pa.side[0].stop = 1;
+    pa.side[0].all = gl.segV;  // V_k in slot k - 1
+    pa.side[0].slot_a = 1;
+    pa.side[0].slot_b = -1;
+    pa.side[0].all_stride = gl.max_rp;
+    pa.side[1].x = gl.xr;
+    pa.side[1].y = gl.yr;
+    pa.side[1].stop = 1;
+    pa.side[1].all = gl.segW;  // V'_j = W_{N-j} in slot N - j
+    pa.side[1].slot_a = -1;
+    pa.side[1].slot_b = N;
+    pa.side[1].all_stride = gl.max_rp;
+    TTC_HIP(launch_pair_lds(x->dtype, pa, 2, s));
+    GradArgs g;
+    std::memset(&g, 0, sizeof(g));
+    g.x = to_dev(x);
+    g.y = to_dev(y);
+    g.segV = gl.segV;
+    g.segW = gl.segW;
+    g.max_rp = gl.max_rp;
+    g.g_global = gl.g_global;
+    g.g_stride = gl.gc.elems;
+    g.gz = d_gz;
+    for (int k = 0; k < N; ++k) {
+      g.dx[k] = d_dx ? d_dx[k] : nullptr;
+      g.dy[k] = d_dy ? d_dy[k] : nullptr;
+    }
+    TTC_HIP(launch_grad_core(x->dtype, g, gl.gc.blocks, gl.gc.global ? 0 : (size_t)gl.gc.elems * sizeof(float), s));
+    return TTC_OK;
+  }
   const int c = ckpt_stride > 0 ? std::min<int>(ckpt_stride, N) : default_stride(N);
   const int ns = (N + c - 1) / c;
   SweepSizing sz;
@@ -712,7 +852,6 @@ ttc_status tt_contract_inner_bwd(const ttc_tt* x, const ttc_tt* y, const double*
     g.dx[k] = d_dx ? d_dx[k] : nullptr;
     g.dy[k] = d_dy ? d_dy[k] : nullptr;
   }
-  hipStream_t s = (hipStream_t)stream;
   TTC_HIP(launch_grad_ckpt(x->dtype, g, sz.lds, s));
   TTC_HIP(launch_grad_seg(x->dtype, g, sz.lds, s));
   TTC_HIP(launch_grad_core(x->dtype, g, gc.blocks, gc.global ? 0 : (size_t)gc.elems * cs, s));

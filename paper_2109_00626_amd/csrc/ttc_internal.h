@@ -111,6 +111,47 @@ struct MpoArgs {
   MpoCore c[TTC_MAX_ORDER];
 };
 
+// ------------------------------------------------- single-pair LDS sweeps
+// One workgroup per side; a side sweeps its pair right to left from
+// V_order = [1] down to V_stop with the LDS-resident step (FP32 or BF16
+// cores, ranks <= 128), and stores
+//   out:   V_stop, row-major R x P (FP32), when set;
+//   all:   every V_k, k = order .. max(stop, 1), row-major, at
+//          all + (slot_a * k + slot_b) * all_stride, when set;
+//   inner: with stop = 1, <X, Y> (FP64) finished with the first cores.
+// A left-to-right sweep is the right-to-left sweep of the reversed pair
+// whose cores have their two rank axes exchanged (see launch_core_reverse):
+// its V'_j is W_{order - j}, in the same orientation.
+struct PairLdsSide {
+  TTDev x, y;
+  int stop;
+  float* out;
+  float* all;
+  int slot_a, slot_b;
+  long all_stride;
+  double* inner;
+};
+struct PairLdsArgs {
+  PairLdsSide side[2];
+};
+// True when the LDS-resident sweep handles the pair (FP32/BF16, ranks <= 128).
+bool pair_lds_ok(const TTDev& x, const TTDev& y);
+hipError_t launch_pair_lds(ttc_dtype dt, const PairLdsArgs& a, int nsides, hipStream_t s);
+
+// dst core j of each list = src core n-1-j with its rank axes exchanged:
+// (R, I, R1) -> (R1, I, R).  esz: element bytes (2 or 4).
+struct CoreRevItem {
+  const void* src;
+  void* dst;
+  int R, I, R1;
+};
+struct CoreRevArgs {
+  int n;
+  int esz;
+  CoreRevItem c[2 * TTC_MAX_ORDER];
+};
+hipError_t launch_core_reverse(const CoreRevArgs& a, hipStream_t s);
+
 // launchers (return the launch status)
 hipError_t launch_sweep(ttc_dtype dt, const SweepArgs& a, int nblocks, size_t lds, hipStream_t s);
 hipError_t launch_meet(ttc_dtype dt, const void* W, const void* V, int n, double* out, hipStream_t s);
