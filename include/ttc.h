@@ -111,8 +111,11 @@ typedef struct {
  * the first step is the paper's K = A_x^T A_y (Section III, Example 1 and
  * Algorithm 2, step 4).  Right to left, V_N = [1] and
  *   V_{k-1} = sum_i G_x^(k)[:, i, :] V_k G_y^(k)[:, i, :]^T.
- * The two sweeps meet at a middle bond c: z = sum W_c .* V_c, accumulated in
- * FP64.  X and Y need equal order and mode sizes; their ranks may differ.
+ * FP32 and BF16 pairs with every rank <= 128 take one right-to-left sweep
+ * whose interface stays in LDS, finished with the first cores in FP64 (no
+ * workspace).  Otherwise the two sweeps meet at a middle bond c:
+ * z = sum W_c .* V_c, accumulated in FP64.  X and Y need equal order and
+ * mode sizes; their ranks may differ.
  * x, y:   descriptors, same dtype.
  * prec:   AUTO, or the precision AUTO would pick.
  * d_out:  device pointer to one double (written).
@@ -216,9 +219,11 @@ ttc_status ttc_mse_loss(const float* d_y, const float* d_t, int64_t n, double* d
  * gradient *d_gz (one device double):
  *   dz/dG_x^(k)[:, i, :] = W_k G_y^(k)[:, i, :] V_{k+1}^T,
  *   dz/dG_y^(k)[:, i, :] = W_k^T G_x^(k)[:, i, :] V_{k+1},
- * with W_k the left interface of core k and V_{k+1} the right one.  Only every
- * ckpt_stride-th interface is kept; the rest are recomputed (ckpt_stride <= 0
- * picks about sqrt(N)).  d_dx[k], d_dy[k]: device buffers shaped like the
+ * with W_k the left interface of core k and V_{k+1} the right one.  FP32 and
+ * BF16 pairs with every rank <= 128 store every interface (2 N max_k R_k P_k
+ * floats of workspace; ckpt_stride is ignored).  Otherwise only every
+ * ckpt_stride-th interface is kept and the rest are recomputed
+ * (ckpt_stride <= 0 picks about sqrt(N)).  d_dx[k], d_dy[k]: device buffers shaped like the
  * cores, same dtype class (FP64 for FP64, FP32 otherwise); either list may
  * be NULL to skip that side.
  * ------------------------------------------------------------------------ */

@@ -69,7 +69,15 @@ def test_inner_validation(lib, abi):
     x = Desc(abi, [3, 4], [1, 2, 1])
     y = Desc(abi, [3, 4], [1, 5, 1])
     assert lib.tt_contract_inner_query(byref(x.s), byref(y.s), 0, byref(need)) == 0
-    assert need.value > 0
+    assert need.value == 0  # FP32, ranks <= 128: one LDS-resident sweep, no workspace
+    x64 = Desc(abi, [3, 4], [1, 2, 1], dtype=0)
+    y64 = Desc(abi, [3, 4], [1, 5, 1], dtype=0)
+    assert lib.tt_contract_inner_query(byref(x64.s), byref(y64.s), 0, byref(need)) == 0
+    assert need.value > 0   # FP64: the two-half sweep with its interface buffers
+    xb = Desc(abi, [3, 4], [1, 200, 1])
+    yb = Desc(abi, [3, 4], [1, 150, 1])
+    assert lib.tt_contract_inner_query(byref(xb.s), byref(yb.s), 0, byref(need)) == 0
+    assert need.value > 0   # ranks above 128 take the same path
     bad = Desc(abi, [3, 4], [2, 2, 1])
     assert status_name(abi, lib.tt_contract_inner_query(byref(bad.s), byref(y.s), 0, byref(need))) == "TTC_ERR_RANK"
     assert b"boundary" in lib.ttc_last_error()
@@ -81,7 +89,7 @@ def test_inner_validation(lib, abi):
     assert status_name(abi, lib.tt_contract_inner_query(byref(x.s), byref(y.s), 1, byref(need))) == "TTC_ERR_UNSUPPORTED"
     # workspace too small and NULL output: rejected before any launch
     out = c_void_p(FAKE)
-    assert status_name(abi, lib.tt_contract_inner(byref(x.s), byref(y.s), 0, out, c_void_p(FAKE), 1, None)) == \
+    assert status_name(abi, lib.tt_contract_inner(byref(x64.s), byref(y64.s), 0, out, c_void_p(FAKE), 1, None)) == \
         "TTC_ERR_WORKSPACE"
     assert status_name(abi, lib.tt_contract_inner(byref(x.s), byref(y.s), 0, None, c_void_p(FAKE), 1 << 30, None)) == \
         "TTC_ERR_NULL"
