@@ -178,7 +178,9 @@ __device__ __forceinline__ void lds_tile(const StepOp& op, const TTC_LDS float* 
   constexpr int esz = sizeof(Tin);
   constexpr int U = TripWidth<KC, PT>::U;
   const int lane = threadIdx.x & 63, li = lane & 15, g = lane >> 4;
-  const int I = op.I, Ka = op.Ka, Kb = op.Kb;
+  // the step's shape is the same in every lane (scalar registers, scalar branches)
+  const int I = __builtin_amdgcn_readfirstlane(op.I), Ka = __builtin_amdgcn_readfirstlane(op.Ka),
+            Kb = __builtin_amdgcn_readfirstlane(op.Kb);
   const int QT = (Kb + 15) >> 4;
   const int ip = lds_pitch(Ka);
   const long ta = (long)op.Ma * I * Ka, tb = (long)op.Nb * I * Kb;
@@ -194,6 +196,7 @@ __device__ __forceinline__ void lds_tile(const StepOp& op, const TTC_LDS float* 
   const TTC_LDS float* inl = In + li * ip + 4 * g;
   if (s0 >= I) return;
   const int step = U * S;
+  const bool afull = (Ka & 15) == 0;  // no partial chunk along a
 
   // current operands as FP32 (masked), next ones as loaded
   f32x4 bx[U][KC], gv[U][PT];
@@ -269,18 +272,28 @@ __device__ __forceinline__ void lds_tile(const StepOp& op, const TTC_LDS float* 
         for (int v = 0; v < 4; ++v) acc[pt] = mfma4(st[u][v], gv[u][pt][v], acc[pt]);
 
     if (!more) break;
-    // the prefetched operands become current (masked past the row ends)
-    bool mb[4];
+    // the prefetched operands become current, masked past the row ends
+    // (only a last, partial 16-wide slice or chunk has such entries)
+    if (nq * 16 + 16 <= Kb) {
 #pragma unroll
-    for (int v = 0; v < 4; ++v) mb[v] = nq * 16 + 4 * g + v < Kb;
+      for (int u = 0; u < U; ++u)
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
+        for (int pt = 0; pt < PT; ++pt) gv[u][pt] = R4::to_f32(gvn[u][pt]);
+    } else {
+      bool mb[4];
 #pragma unroll
-      for (int pt = 0; pt < PT; ++pt) gv[u][pt] = R4::to_f32(gvn[u][pt], mb);
-      if (nq == 0) {
+      for (int v = 0; v < 4; ++v) mb[v] = nq * 16 + 4 * g + v < Kb;
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int pt = 0; pt < PT; ++pt) gv[u][pt] = R4::to_f32(gvn[u][pt], mb);
+    }
+    if (nq == 0) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
 #pragma unroll
         for (int kc = 0; kc < KC - 1; ++kc) bx[u][kc] = R4::to_f32(bxn[u][kc]);
-        bx[u][KC - 1] = R4::to_f32(bxn[u][KC - 1], ma);
+        bx[u][KC - 1] = afull ? R4::to_f32(bxn[u][KC - 1]) : R4::to_f32(bxn[u][KC - 1], ma);
       }
     }
     i = ni;
