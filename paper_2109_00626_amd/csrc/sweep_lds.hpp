@@ -301,6 +301,175 @@ __device__ __forceinline__ void lds_tile(const StepOp& op, const TTC_LDS float* 
   }
 }
 
+// Two a-tiles of one wave in one pass (all mode indices, S = 1), for shapes
+// that take one mode index per trip: the In^T reads and the G_B operands are
+// shared by the tiles, so a trip carries twice the MFMA work per load.  The
+// G_A rows of both tiles are reloaded once per mode index, right after the
+// last slice's stage-1 products have consumed them (their latency is covered
+// by that slice's stage 2).
+template <typename Tin, int KC, int PT>
+__device__ __forceinline__ void lds_tile2(const StepOp& op, const TTC_LDS float* __restrict__ In, int at0, int at1,
+                                          f32x4 (&acc0)[SW_MAXT], f32x4 (&acc1)[SW_MAXT]) {
+  typedef Raw4<Tin> R4;
+  typedef typename R4::type raw_t;
+  constexpr int esz = sizeof(Tin);
+  // FP32 loads land in the operand registers themselves (no raw copy)
+  constexpr bool kDirect = sizeof(raw_t) == sizeof(f32x4);
+  const int lane = threadIdx.x & 63, li = lane & 15, g = lane >> 4;
+  const int I = __builtin_amdgcn_readfirstlane(op.I), Ka = __builtin_amdgcn_readfirstlane(op.Ka),
+            Kb = __builtin_amdgcn_readfirstlane(op.Kb);
+  const int QT = (Kb + 15) >> 4;
+  const int ip = lds_pitch(Ka);
+  const long ta = (long)op.Ma * I * Ka, tb = (long)op.Nb * I * Kb;
+  const int aoff0 = ((at0 * 16 + li) * I * Ka + 4 * g) * esz;
+  const int aoff1 = ((at1 * 16 + li) * I * Ka + 4 * g) * esz;
+  int boff[PT];
+#pragma unroll
+  for (int pt = 0; pt < PT; ++pt) boff[pt] = ((pt * 16 + li) * I * Kb + 4 * g) * esz;
+  bool ma[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) ma[u] = (KC - 1) * 16 + 4 * g + u < Ka;
+  const bool afull = (Ka & 15) == 0;
+  const TTC_LDS float* inl = In + li * ip + 4 * g;
+
+  f32x4 bx0[KC], bx1[KC], gv[PT];
+  raw_t br0[kDirect ? 1 : KC], br1[kDirect ? 1 : KC], gvn[PT];
+  // G_A rows of mode index ii for both tiles (into the operands for FP32)
+  auto load_a = [&](int ii) {
+    const CoreRes ra = core_rsrc(op.ga, (long)ii * Ka, ta, esz);
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc) {
+      if constexpr (kDirect) {
+        bx0[kc] = R4::to_f32(R4::load(ra, aoff0 + kc * 16 * esz));
+        bx1[kc] = R4::to_f32(R4::load(ra, aoff1 + kc * 16 * esz));
+      } else {
+        br0[kc] = R4::load(ra, aoff0 + kc * 16 * esz);
+        br1[kc] = R4::load(ra, aoff1 + kc * 16 * esz);
+      }
+    }
+  };
+  // the loaded G_A rows as masked FP32 operands
+  auto finish_a = [&]() {
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc) {
+      const bool last = kc == KC - 1 && !afull;
+      if constexpr (kDirect) {
+        if (last) {
+          bx0[kc] = R4::to_f32(bx0[kc], ma);
+          bx1[kc] = R4::to_f32(bx1[kc], ma);
+        }
+      } else {
+        bx0[kc] = last ? R4::to_f32(br0[kc], ma) : R4::to_f32(br0[kc]);
+        bx1[kc] = last ? R4::to_f32(br1[kc], ma) : R4::to_f32(br1[kc]);
+      }
+    }
+  };
+  {
+    load_a(0);
+    const CoreRes rb = core_rsrc(op.gb, 0, tb, esz);
+#pragma unroll
+    for (int pt = 0; pt < PT; ++pt) gvn[pt] = R4::load(rb, boff[pt]);
+    bool mb[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) mb[v] = 4 * g + v < Kb;
+    finish_a();
+#pragma unroll
+    for (int pt = 0; pt < PT; ++pt) gv[pt] = R4::to_f32(gvn[pt], mb);
+    __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+  }
+  int i = 0, qt = 0;
+  for (;;) {
+    int ni = i, nq = qt + 1;
+    if (nq == QT) {
+      nq = 0;
+      ni = i + 1;
+    }
+    const bool more = ni < I;
+    if (more) {
+      const CoreRes rb = core_rsrc(op.gb, (long)ni * Kb + nq * 16, tb, esz);
+#pragma unroll
+      for (int pt = 0; pt < PT; ++pt) gvn[pt] = R4::load(rb, boff[pt]);
+    }
+    f32x4 st0 = {0.f, 0.f, 0.f, 0.f}, st1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc) {
+      const f32x4 av = *reinterpret_cast<const TTC_LDS f32x4*>(inl + qt * 16 * ip + kc * 16);
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        st0 = mfma4(av[w], bx0[kc][w], st0);
+        st1 = mfma4(av[w], bx1[kc][w], st1);
+      }
+    }
+    // G_A rows of the next mode index (this slice's stage 1 was their last use)
+    const bool reload = more && nq == 0;
+    if (reload) load_a(ni);
+#pragma unroll
+    for (int pt = 0; pt < PT; ++pt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        acc0[pt] = mfma4(st0[v], gv[pt][v], acc0[pt]);
+        acc1[pt] = mfma4(st1[v], gv[pt][v], acc1[pt]);
+      }
+    if (!more) break;
+    if (nq * 16 + 16 <= Kb) {
+#pragma unroll
+      for (int pt = 0; pt < PT; ++pt) gv[pt] = R4::to_f32(gvn[pt]);
+    } else {
+      bool mb[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) mb[v] = nq * 16 + 4 * g + v < Kb;
+#pragma unroll
+      for (int pt = 0; pt < PT; ++pt) gv[pt] = R4::to_f32(gvn[pt], mb);
+    }
+    if (reload) finish_a();
+    i = ni;
+    qt = nq;
+  }
+}
+
+// Both a-tiles at0, at1 of one wave over every mode index: in one pass for
+// shapes that take one mode index per trip, else one pass per tile.
+template <typename Tin, int KC, int PT>
+__device__ __forceinline__ void lds_pair(const StepOp& op, const TTC_LDS float* In, int at0, int at1,
+                                         f32x4 (&acc0)[SW_MAXT], f32x4 (&acc1)[SW_MAXT]) {
+  if constexpr (TripWidth<KC, PT>::U == 1) {
+    lds_tile2<Tin, KC, PT>(op, In, at0, at1, acc0, acc1);
+  } else {
+    lds_tile<Tin, KC, PT>(op, In, at0, 0, 1, acc0);
+    lds_tile<Tin, KC, PT>(op, In, at1, 0, 1, acc1);
+  }
+}
+
+template <typename Tin, int KC>
+__device__ __forceinline__ void lds_pair_p(const StepOp& op, const TTC_LDS float* In, int at0, int at1,
+                                           f32x4 (&acc0)[SW_MAXT], f32x4 (&acc1)[SW_MAXT]) {
+  switch ((op.Nb + 15) >> 4) {
+    case 1: lds_pair<Tin, KC, 1>(op, In, at0, at1, acc0, acc1); break;
+    case 2: lds_pair<Tin, KC, 2>(op, In, at0, at1, acc0, acc1); break;
+    case 3: lds_pair<Tin, KC, 3>(op, In, at0, at1, acc0, acc1); break;
+    case 4: lds_pair<Tin, KC, 4>(op, In, at0, at1, acc0, acc1); break;
+    case 5: lds_pair<Tin, KC, 5>(op, In, at0, at1, acc0, acc1); break;
+    case 6: lds_pair<Tin, KC, 6>(op, In, at0, at1, acc0, acc1); break;
+    case 7: lds_pair<Tin, KC, 7>(op, In, at0, at1, acc0, acc1); break;
+    default: lds_pair<Tin, KC, 8>(op, In, at0, at1, acc0, acc1); break;
+  }
+}
+
+template <typename Tin>
+__device__ __forceinline__ void lds_pair_v(const StepOp& op, const TTC_LDS float* In, int at0, int at1,
+                                           f32x4 (&acc0)[SW_MAXT], f32x4 (&acc1)[SW_MAXT]) {
+  switch ((op.Ka + 15) >> 4) {
+    case 1: lds_pair_p<Tin, 1>(op, In, at0, at1, acc0, acc1); break;
+    case 2: lds_pair_p<Tin, 2>(op, In, at0, at1, acc0, acc1); break;
+    case 3: lds_pair_p<Tin, 3>(op, In, at0, at1, acc0, acc1); break;
+    case 4: lds_pair_p<Tin, 4>(op, In, at0, at1, acc0, acc1); break;
+    case 5: lds_pair_p<Tin, 5>(op, In, at0, at1, acc0, acc1); break;
+    case 6: lds_pair_p<Tin, 6>(op, In, at0, at1, acc0, acc1); break;
+    case 7: lds_pair_p<Tin, 7>(op, In, at0, at1, acc0, acc1); break;
+    default: lds_pair_p<Tin, 8>(op, In, at0, at1, acc0, acc1); break;
+  }
+}
+
 template <typename Tin, int KC>
 __device__ __forceinline__ void lds_tile_p(const StepOp& op, const TTC_LDS float* In, int at, int s0, int S,
                                            f32x4 (&acc)[SW_MAXT]) {
@@ -416,15 +585,22 @@ __device__ __forceinline__ void lds_step_inplace(const StepOp& op, TTC_LDS float
   }
   const int items = RT * S;
   f32x4 acc[SW_MAXT], keep[SW_MAXT];
+  if (S == 1 && w + NW < items) {
+    // two a-tiles, every mode index: one pass where the shape allows
+#pragma unroll
+    for (int t = 0; t < SW_MAXT; ++t) keep[t] = acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    lds_pair_v<Tin>(op, Buf, w, w + NW, keep, acc);
+  } else {
 #pragma unroll 1
-  for (int it = 0; it < 2; ++it) {
-    const int item = w + it * NW;
+    for (int it = 0; it < 2; ++it) {
+      const int item = w + it * NW;
 #pragma unroll
-    for (int t = 0; t < SW_MAXT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-    if (item < items) lds_tile_v<Tin>(op, Buf, item % RT, item / RT, S, acc);
-    if (it == 0) {
+      for (int t = 0; t < SW_MAXT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+      if (item < items) lds_tile_v<Tin>(op, Buf, item % RT, item / RT, S, acc);
+      if (it == 0) {
 #pragma unroll
-      for (int t = 0; t < SW_MAXT; ++t) keep[t] = acc[t];
+        for (int t = 0; t < SW_MAXT; ++t) keep[t] = acc[t];
+      }
     }
   }
   __syncthreads();  // In fully read
