@@ -272,7 +272,9 @@ ttc_status tt_batch_plan_info(const ttc_plan* plan, int64_t* junction_offsets, d
 /* The schedule the plan's tuner selected (host ints; any may be NULL):
  * mode 0 = persistent kernel with chained-MFMA steps, 1 = one launch per
  * sweep level, 2 = persistent kernel with LDS-resident interfaces, 3 = the
- * same with one interface buffer per workgroup updated in place;
+ * same with one interface buffer per workgroup updated in place, 4 (BF16
+ * cores only) = mode 3 on BF16 MFMA with the interface held as a BF16 hi /
+ * lo pair (16 significant bits);
  * threads = workgroup size; wg_per_cu = workgroups per compute unit. */
 ttc_status tt_batch_plan_config(const ttc_plan* plan, int32_t* mode, int32_t* threads, int32_t* wg_per_cu);
 ttc_status tt_batch_run(ttc_plan* plan, double* d_inner, float* d_junction, void* stream);

@@ -299,7 +299,7 @@ class BatchPlan:
         self.flops, self.bytes = fl.value, by.value
         m, t, pc = c_int32(), c_int32(), c_int32()
         _check(_lib.tt_batch_plan_config(self._h, byref(m), byref(t), byref(pc)))
-        self.config = {"mode": ("persistent", "levels", "lds", "lds1")[m.value], "threads": t.value, "wg_per_cu": pc.value}
+        self.config = {"mode": ("persistent", "levels", "lds", "lds1", "lds1b")[m.value], "threads": t.value, "wg_per_cu": pc.value}
 
     def outputs(self):
         inner = torch.empty(self.n, dtype=torch.float64, device=self.device)

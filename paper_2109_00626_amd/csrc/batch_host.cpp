@@ -152,6 +152,17 @@ int lds_iface_elems_h(int R, int P) {
   return std::max(pad16h(P) * (pad16h(R) + 4), pad16h(R) * (pad16h(P) + 4));
 }
 
+// BF16 elements of one plane of the BF16-MFMA variant's interface (rows
+// padded to 16, pitch padded + 8); its two planes take as many bytes as this
+// many floats.
+int lds16_iface_elems_h(int R, int P) {
+  return std::max(pad16h(P) * (pad16h(R) + 8), pad16h(R) * (pad16h(P) + 8));
+}
+
+bool lds_mode(int mode) { return mode == 2 || mode == 3 || mode == 4; }
+
+int lds_variant(int mode) { return mode == 4 ? kBatchLdsB16 : mode == 3 ? kBatchLdsInPlace : kBatchLdsTwo; }
+
 // Time model of the LDS-resident kernel for one pair, in shader cycles of
 // one workgroup of four waves: per step a fixed cost (set-up, the first
 // loads' latency, barriers), a cost per loop iteration of the busiest wave
@@ -273,12 +284,12 @@ hipError_t run_persistent(ttc_plan* P, double* inner, float* junc, hipStream_t s
 hipError_t run_lds(ttc_plan* P, double* inner, float* junc, hipStream_t s) {
   BatchArgs a = make_args(P, P->d_begin, P->d_order, inner, junc, P->lds_elems, P->grid);
   a.claim = P->d_claim;
-  return launch_batch_lds(P->dt, a, P->grid, P->cfg.threads, P->mode == 3, s);
+  return launch_batch_lds(P->dt, a, P->grid, P->cfg.threads, lds_variant(P->mode), s);
 }
 
 hipError_t run_mode(ttc_plan* P, double* inner, float* junc, hipStream_t s) {
   if (P->mode == 1) return run_levels(P, inner, junc, s);
-  if (P->mode == 2 || P->mode == 3) return run_lds(P, inner, junc, s);
+  if (lds_mode(P->mode)) return run_lds(P, inner, junc, s);
   return run_persistent(P, inner, junc, s);
 }
 
@@ -293,7 +304,7 @@ ttc_status upload_assignment(ttc_plan* P, const LaunchCfg& c, int* grid_out, int
   const int grid = std::min(P->cus * c.per_cu, std::max(P->n, 1));
   std::vector<int> begin, order;
   lpt_assign(P->cost, grid, &begin, &order);
-  if (c.mode == 2 || c.mode == 3) {
+  if (lds_mode(c.mode)) {
     // claimed one by one at run time: the whole list, longest first
     order.resize(P->n);
     for (int i = 0; i < P->n; ++i) order[i] = i;
@@ -321,7 +332,7 @@ std::string cache_key(const ttc_plan* P) {
   mix(P->ops);
   mix(P->dt);
   std::ostringstream os;
-  os << "gfx950|abi" << TTC_ABI_VERSION << "|s4|" << std::hex << h;
+  os << "gfx950|abi" << TTC_ABI_VERSION << "|s5|" << std::hex << h;
   return os.str();
 }
 
@@ -353,13 +364,16 @@ void cache_store(const std::string& key, const LaunchCfg& c) {
 
 ttc_status autotune(ttc_plan* P) {
   const std::string key = cache_key(P);
-  const char* forced = std::getenv("TTC_BATCH_MODE");  // testing: levels | persistent | lds | lds1
+  const char* forced = std::getenv("TTC_BATCH_MODE");  // testing: levels | persistent | lds | lds1 | lds1b
   int want = -1;
   if (forced) {
     if (std::strcmp(forced, "persistent") == 0) want = 0;
     if (std::strcmp(forced, "levels") == 0) want = 1;
     if (std::strcmp(forced, "lds") == 0) want = 2;
     if (std::strcmp(forced, "lds1") == 0) want = 3;
+    if (std::strcmp(forced, "lds1b") == 0) want = 4;
+    // the BF16-MFMA variant takes BF16 cores only; FP32 plans keep the tuner's choice
+    if (want == 4 && P->dt != TTC_BF16) want = -1;
   }
   LaunchCfg best;
   if (cache_lookup(key, &best) && (want < 0 || want == best.mode)) {
@@ -368,6 +382,8 @@ ttc_status autotune(ttc_plan* P) {
     return upload_assignment(P, best, &P->grid, &P->lds_elems);
   }
   std::vector<LaunchCfg> cands;
+  if (P->dt == TTC_BF16 && (want < 0 || want == 4))
+    for (int pc = 1; pc <= lds_kernel_per_cu(P, 1); ++pc) cands.push_back({4, 256, pc});
   if (want < 0 || want == 3)
     for (int pc = 1; pc <= lds_kernel_per_cu(P, 1); ++pc) cands.push_back({3, 256, pc});
   if (want < 0 || want == 2) {
@@ -487,8 +503,12 @@ ttc_status tt_batch_plan_create(const ttc_pair* pairs, int32_t n, uint32_t ops, 
     P->bytes += by;
     P->cost[i] = pair_time_model(h);
     for (int b = 1; b <= N; ++b) P->max_rp = std::max<long>(P->max_rp, (long)h.rx[b] * ((h.ry[b] & 1) ? h.ry[b] : h.ry[b] + 1));
-    for (int b = 1; b <= N; ++b) P->buf_elems = std::max(P->buf_elems, lds_iface_elems_h(h.rx[b], h.ry[b]));
+    for (int b = 1; b <= N; ++b) {
+      P->buf_elems = std::max(P->buf_elems, lds_iface_elems_h(h.rx[b], h.ry[b]));
+      if (dt == TTC_BF16) P->buf_elems = std::max(P->buf_elems, lds16_iface_elems_h(h.rx[b], h.ry[b]));
+    }
   }
+  P->buf_elems = (P->buf_elems + 7) & ~7;  // BF16 lo plane at a 16-byte boundary
   hipError_t e = hipGetDevice(&P->device);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&P->cus, hipDeviceAttributeMultiprocessorCount, P->device);
   if (e != hipSuccess) {
@@ -696,11 +716,11 @@ ttc_status tt_batch_run_traced(ttc_plan* P, double* d_inner, float* d_junction, 
   if ((P->ops & TTC_OP_INNER) && !d_inner) return fail(TTC_ERR_NULL, "d_inner is NULL");
   if ((P->ops & TTC_OP_SUFFIX2) && !d_junction) return fail(TTC_ERR_NULL, "d_junction is NULL");
   if (!d_clock) return fail(TTC_ERR_NULL, "d_clock is NULL");
-  if (P->mode != 2 && P->mode != 3) return fail(TTC_ERR_UNSUPPORTED, "tracing needs an LDS-resident schedule");
+  if (!lds_mode(P->mode)) return fail(TTC_ERR_UNSUPPORTED, "tracing needs an LDS-resident schedule");
   BatchArgs a = make_args(P, P->d_begin, P->d_order, d_inner, d_junction, P->lds_elems, P->grid);
   a.clock = reinterpret_cast<long long*>(d_clock);
   a.claim = P->d_claim;
-  TTC_HIP(launch_batch_lds(P->dt, a, P->grid, P->cfg.threads, P->mode == 3, (hipStream_t)stream));
+  TTC_HIP(launch_batch_lds(P->dt, a, P->grid, P->cfg.threads, lds_variant(P->mode), (hipStream_t)stream));
   return TTC_OK;
 }
 
@@ -712,7 +732,7 @@ ttc_status tt_batch_run_plain(ttc_plan* P, double* d_inner, float* d_junction, v
   // one launch per pair of the LDS-resident kernel (one workgroup each)
   for (int p = 0; p < P->n; ++p) {
     BatchArgs a = make_args(P, P->d_01, P->d_ident + p, d_inner, d_junction, 0, 1);
-    TTC_HIP(launch_batch_lds(P->dt, a, 1, 256, false, s));
+    TTC_HIP(launch_batch_lds(P->dt, a, 1, 256, kBatchLdsTwo, s));
   }
   return TTC_OK;
 }

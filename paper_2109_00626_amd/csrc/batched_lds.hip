@@ -14,24 +14,29 @@
 // contraction over the last two positions) when asked, and finishes
 // <X, Y> = sum_i G_x^(0)[0, i, :] V_1 G_y^(0)[0, i, :]^T with an MFMA
 // product and an FP64 reduction.  The dynamic LDS holds two interface
-// buffers of `buf_elems` floats used alternately, or (in-place variant) one
-// buffer that each step overwrites.
-#include "sweep_lds.hpp"
+// buffers of `buf_elems` floats used alternately, or (in-place variants) one
+// buffer that each step overwrites: FP32, or for BF16 cores on BF16 MFMA two
+// BF16 planes (hi, lo) of `buf_elems` elements each (sweep_lds16.hpp).
+#include "sweep_lds16.hpp"
 #include "ttc_batch.h"
 #include "ttc_device.hpp"
 
 namespace ttc {
 
 // ONE: a single interface buffer updated in place (two workgroups per CU);
-// otherwise two buffers used alternately.
-template <typename Tin, int NT, bool ONE>
+// otherwise two buffers used alternately.  M16 (BF16 cores, in place): the
+// steps run on BF16 MFMA with the interface as BF16 hi / lo planes.
+template <typename Tin, int NT, bool ONE, bool M16 = false>
 __global__ __launch_bounds__(NT, ONE ? 2 : 1) void batch_lds_kernel(BatchArgs a) {
   constexpr int NW = NT / 64;
+  static_assert(!M16 || (ONE && sizeof(Tin) == 2), "BF16 MFMA steps: BF16 cores, in place");
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double red[16];
   __shared__ TTDev sx, sy;
   TTC_LDS float* const buf0 = (TTC_LDS float*)(smem);
   TTC_LDS float* const buf1 = ONE ? buf0 : buf0 + a.buf_elems;
+  TTC_LDS uint16_t* const pl = (TTC_LDS uint16_t*)(smem);  // M16: hi plane; lo plane at pl + lo
+  const int lo = a.buf_elems;
   __shared__ int claimed;
   const bool dyn = a.claim != nullptr;
   const int end = dyn ? a.npairs : a.wg_begin[blockIdx.x + 1];
@@ -66,8 +71,16 @@ __global__ __launch_bounds__(NT, ONE ? 2 : 1) void batch_lds_kernel(BatchArgs a)
         sy.ranks[e] = ip[2 * N + 1 + e];
       }
     }
-    // V_N = [1], padded to a 16 x 16 block (pitch lds_pitch(1))
-    for (int e = threadIdx.x; e < 16 * lds_pitch(1); e += NT) buf0[e] = (e == 0) ? 1.f : 0.f;
+    // V_N = [1], padded to a 16 x 16 block (pitch lds_pitch(1), or
+    // lds16_pitch(1) in both planes)
+    if constexpr (M16) {
+      for (int e = threadIdx.x; e < 16 * lds16_pitch(1); e += NT) {
+        pl[e] = (e == 0) ? (uint16_t)0x3F80u : (uint16_t)0;
+        pl[lo + e] = 0;
+      }
+    } else {
+      for (int e = threadIdx.x; e < 16 * lds_pitch(1); e += NT) buf0[e] = (e == 0) ? 1.f : 0.f;
+    }
     __syncthreads();
     const int N = sx.order;
     TTC_LDS float* in = buf0;
@@ -93,16 +106,25 @@ __global__ __launch_bounds__(NT, ONE ? 2 : 1) void batch_lds_kernel(BatchArgs a)
         op.Nb = sy.ranks[k];
         op.Kb = sy.ranks[k + 1];
       }
-      if constexpr (ONE) lds_step_inplace<Tin, NW>(op, in, yf == yf_next);
+      if constexpr (M16) lds16_step_inplace<NW>(op, pl, lo, yf == yf_next);
+      else if constexpr (ONE) lds_step_inplace<Tin, NW>(op, in, yf == yf_next);
       else lds_step<Tin, NW>(op, in, out, yf == yf_next);
       if (k == N - 2 && (a.ops & TTC_OP_SUFFIX2)) {
         // V_{N-2} (R x P) in the layout chosen for the next step
         const int R = sx.ranks[k], P = sy.ranks[k];
         const long jo = a.pairs[p].jout;
-        const int tp = lds_pitch(R), np = lds_pitch(P);
-        for (int e = threadIdx.x; e < R * P; e += NT) {
-          const int r = e / P, c = e - r * P;
-          a.junction[jo + e] = yf_next ? out[r * np + c] : out[c * tp + r];
+        if constexpr (M16) {
+          const int tp = lds16_pitch(R), np = lds16_pitch(P);
+          for (int e = threadIdx.x; e < R * P; e += NT) {
+            const int r = e / P, c = e - r * P;
+            a.junction[jo + e] = lds16_get(pl, lo, yf_next ? r * np + c : c * tp + r);
+          }
+        } else {
+          const int tp = lds_pitch(R), np = lds_pitch(P);
+          for (int e = threadIdx.x; e < R * P; e += NT) {
+            const int r = e / P, c = e - r * P;
+            a.junction[jo + e] = yf_next ? out[r * np + c] : out[c * tp + r];
+          }
         }
       }
       TTC_LDS float* t = in;
@@ -113,7 +135,9 @@ __global__ __launch_bounds__(NT, ONE ? 2 : 1) void batch_lds_kernel(BatchArgs a)
         a.clock[3L * a.npairs + 32L * p + (N - 1 - k)] = (long long)__builtin_readcyclecounter();
     }
     if (a.ops & TTC_OP_INNER) {
-      double s = lds_final<Tin, NW>(sx.cores[0], sy.cores[0], sx.modes[0], sx.ranks[1], sy.ranks[1], in);
+      double s;
+      if constexpr (M16) s = lds16_final<NW>(sx.cores[0], sy.cores[0], sx.modes[0], sx.ranks[1], sy.ranks[1], pl, lo);
+      else s = lds_final<Tin, NW>(sx.cores[0], sy.cores[0], sx.modes[0], sx.ranks[1], sy.ranks[1], in);
       s = wg_sum_f64(s, red);
       if (threadIdx.x == 0) a.inner[p] = s;
     }
@@ -145,7 +169,8 @@ hipError_t batch_lds_set_lds(int bytes) {
     if (e != hipSuccess) return e;
   }
   const void* one[] = {reinterpret_cast<const void*>(&batch_lds_kernel<float, 256, true>),
-                       reinterpret_cast<const void*>(&batch_lds_kernel<bf16_t, 256, true>)};
+                       reinterpret_cast<const void*>(&batch_lds_kernel<bf16_t, 256, true>),
+                       reinterpret_cast<const void*>(&batch_lds_kernel<bf16_t, 256, true, true>)};
   for (const void* k : one) {
     hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes / 2);
     if (e != hipSuccess) return e;
@@ -153,8 +178,14 @@ hipError_t batch_lds_set_lds(int bytes) {
   return hipSuccess;
 }
 
-hipError_t launch_batch_lds(ttc_dtype dt, const BatchArgs& a, int grid, int threads, bool inplace, hipStream_t s) {
-  if (inplace) {
+hipError_t launch_batch_lds(ttc_dtype dt, const BatchArgs& a, int grid, int threads, int variant, hipStream_t s) {
+  if (variant == kBatchLdsB16) {
+    if (dt != TTC_BF16) return hipErrorInvalidValue;
+    const size_t lds = (size_t)a.buf_elems * sizeof(float);
+    hipLaunchKernelGGL((batch_lds_kernel<bf16_t, 256, true, true>), dim3(grid), dim3(256), lds, s, a);
+    return hipGetLastError();
+  }
+  if (variant == kBatchLdsInPlace) {
     const size_t lds = (size_t)a.buf_elems * sizeof(float);
     if (dt == TTC_BF16) hipLaunchKernelGGL((batch_lds_kernel<bf16_t, 256, true>), dim3(grid), dim3(256), lds, s, a);
     else hipLaunchKernelGGL((batch_lds_kernel<float, 256, true>), dim3(grid), dim3(256), lds, s, a);

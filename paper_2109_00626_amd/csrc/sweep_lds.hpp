@@ -500,37 +500,65 @@ __device__ __forceinline__ void lds_tile_v(const StepOp& op, const TTC_LDS float
   }
 }
 
-// Store (first) or add the a-tile `at` of Out: acc[pt][v] is
+// Store (FIRST) or add the a-tile `at` of Out: acc[pt][v] is
 // Out[at*16 + 4g + v, pt*16 + li].  native: Out^T layout (rows b, pitch
 // lds_pitch(Ma)), one 16-byte write per tile; else Out layout (rows a,
-// pitch lds_pitch(Nb)).  Entries outside Ma x Nb are written as zeros.
-__device__ __forceinline__ void lds_put(TTC_LDS float* Out, bool native, int Ma, int Nb, int at,
-                                        const f32x4 (&acc)[SW_MAXT], bool first) {
+// pitch lds_pitch(Nb)).  Entries outside Ma x Nb are written as zeros.  When
+// adding, every old value is read before any is written, so the reads
+// overlap instead of each waiting for the previous write.
+template <bool FIRST>
+__device__ __forceinline__ void lds_put_t(TTC_LDS float* Out, bool native, int Ma, int Nb, int at,
+                                          const f32x4 (&acc)[SW_MAXT]) {
   const int lane = threadIdx.x & 63, li = lane & 15, g = lane >> 4;
   const int PT = (Nb + 15) >> 4;
   const int a0 = at * 16 + 4 * g;
   const int pitch = native ? lds_pitch(Ma) : lds_pitch(Nb);
+  f32x4 v[SW_MAXT];
 #pragma unroll
   for (int pt = 0; pt < SW_MAXT; ++pt) {
-    if (pt < PT) {
-      const int b = pt * 16 + li;
-      f32x4 v;
+    const int b = pt * 16 + li;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) v[u] = (a0 + u < Ma && b < Nb) ? acc[pt][u] : 0.f;
-      if (native) {
-        TTC_LDS f32x4* q = reinterpret_cast<TTC_LDS f32x4*>(Out + b * pitch + a0);
-        if (first) *q = v;
-        else *q = *q + v;
-      } else {
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          TTC_LDS float* q = Out + (a0 + u) * pitch + b;
-          if (first) *q = v[u];
-          else *q = *q + v[u];
-        }
-      }
-    }
+    for (int u = 0; u < 4; ++u) v[pt][u] = (a0 + u < Ma && b < Nb) ? acc[pt][u] : 0.f;
   }
+  if (native) {
+    if (!FIRST) {
+      f32x4 old[SW_MAXT];
+#pragma unroll
+      for (int pt = 0; pt < SW_MAXT; ++pt)
+        if (pt < PT) old[pt] = *reinterpret_cast<TTC_LDS f32x4*>(Out + (pt * 16 + li) * pitch + a0);
+#pragma unroll
+      for (int pt = 0; pt < SW_MAXT; ++pt)
+        if (pt < PT) v[pt] = v[pt] + old[pt];
+    }
+#pragma unroll
+    for (int pt = 0; pt < SW_MAXT; ++pt)
+      if (pt < PT) *reinterpret_cast<TTC_LDS f32x4*>(Out + (pt * 16 + li) * pitch + a0) = v[pt];
+  } else {
+    if (!FIRST) {
+      float old[SW_MAXT][4];
+#pragma unroll
+      for (int pt = 0; pt < SW_MAXT; ++pt)
+        if (pt < PT)
+#pragma unroll
+          for (int u = 0; u < 4; ++u) old[pt][u] = Out[(a0 + u) * pitch + pt * 16 + li];
+#pragma unroll
+      for (int pt = 0; pt < SW_MAXT; ++pt)
+        if (pt < PT)
+#pragma unroll
+          for (int u = 0; u < 4; ++u) v[pt][u] += old[pt][u];
+    }
+#pragma unroll
+    for (int pt = 0; pt < SW_MAXT; ++pt)
+      if (pt < PT)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) Out[(a0 + u) * pitch + pt * 16 + li] = v[pt][u];
+  }
+}
+
+__device__ __forceinline__ void lds_put(TTC_LDS float* Out, bool native, int Ma, int Nb, int at,
+                                        const f32x4 (&acc)[SW_MAXT], bool first) {
+  if (first) lds_put_t<true>(Out, native, Ma, Nb, at, acc);
+  else lds_put_t<false>(Out, native, Ma, Nb, at, acc);
 }
 
 // One step by the NW waves of the workgroup.  Output tiles (16 rows of a)

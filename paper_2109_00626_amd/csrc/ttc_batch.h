@@ -28,7 +28,7 @@ struct BatchArgs {
   long t_stride;
   double* inner;
   float* junction;
-  int buf_elems;         // LDS-resident sweep: floats per interface buffer
+  int buf_elems;         // LDS-resident sweep: floats per interface buffer (BF16 planes: elements per plane)
   long long* clock;      // tracing (may be null): start/end clock per pair, then the workgroup
   int npairs;
   int* claim;            // LDS-resident kernels: when set, workgroups claim positions of `order`
@@ -63,6 +63,10 @@ hipError_t launch_level(ttc_dtype dt, const LevelArgs& a, int nitems, size_t lds
 hipError_t launch_meet_level(ttc_dtype dt, const LevelArgs& a, int npairs, size_t lds, hipStream_t s);
 hipError_t launch_batch(ttc_dtype dt, const BatchArgs& a, int grid, int threads, hipStream_t s);
 hipError_t batch_lds_set_lds(int bytes);
-hipError_t launch_batch_lds(ttc_dtype dt, const BatchArgs& a, int grid, int threads, bool inplace, hipStream_t s);
+// LDS-resident kernel variants: two FP32 interface buffers, one FP32 buffer
+// updated in place, or (BF16 cores only) in place on BF16 MFMA with the
+// interface as BF16 hi / lo planes.
+enum { kBatchLdsTwo = 0, kBatchLdsInPlace = 1, kBatchLdsB16 = 2 };
+hipError_t launch_batch_lds(ttc_dtype dt, const BatchArgs& a, int grid, int threads, int variant, hipStream_t s);
 
 }  // namespace ttc

@@ -36,31 +36,52 @@ def _check_pairs(plan, inner, junc, cores64, idx, tol):
     return worst
 
 
-@pytest.fixture(params=["lds1", "lds", "levels", "persistent"])
+# Arithmetic-only bound for BF16 cores (against the oracle on the rounded
+# values): FP32 steps round at 2^-24 per operation; the BF16-MFMA schedule
+# carries the interface and each per-index product as a BF16 hi / lo pair
+# (16 significant bits), so each of a sweep's <= 12 steps adds about 2^-17
+# relative, and 1e-4 leaves a wide margin over the ~1e-5 worst case.
+ARITH_BF16 = {"lds1b": 1e-4}
+ARITH_BF16_DEFAULT = 1e-5
+
+
+@pytest.fixture(params=["lds1", "lds1b", "lds", "levels", "persistent"])
 def batch_mode(request, monkeypatch):
     """Every batched schedule (the autotuner picks one by timing)."""
     monkeypatch.setenv("TTC_BATCH_MODE", request.param)
     return request.param
 
 
+def _skip_f32_only_bf16(batch_mode, dtype):
+    if batch_mode == "lds1b" and dtype != "bf16":
+        pytest.skip("the BF16-MFMA schedule takes BF16 cores only")
+
+
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
 def test_batch_small_uneven(ttc, dtype, batch_mode):
+    _skip_f32_only_bf16(batch_mode, dtype)
     shapes = C.batch_pair_shapes(C.SEED_BATCH, 40)
     # plus degenerate shapes: order 3 with rank-1 bonds, order 12 small ranks
     shapes.append((C.TTShape([4, 4, 4], [1, 1, 1, 1]), C.TTShape([4, 4, 4], [1, 1, 1, 1])))
     shapes.append((C.TTShape([5] * 12, [1] + [3] * 11 + [1]), C.TTShape([5] * 12, [1] + [2] * 11 + [1])))
-    cores64, gpu = [], []
+    cores64, seen, gpu = [], [], []
     for p, (sx, sy) in enumerate(shapes):
         x = C.gen_tt_np(C.SEED_BATCH, 1 + 2 * p, sx)
         y = C.gen_tt_np(C.SEED_BATCH, 2 + 2 * p, sy)
         xg, xs = to_gpu(x, dtype)
         yg, ys = to_gpu(y, dtype)
         cores64.append((x, y) if dtype == "bf16" else (xs, ys))
+        seen.append((xs, ys))
         gpu.append((xg, yg))
     plan = ttc.BatchPlan(gpu)
+    if batch_mode in ("lds1", "lds1b", "lds", "levels", "persistent"):
+        assert plan.config["mode"] == batch_mode
     inner, junc = plan.run()
     inner = to_np(inner)
     _check_pairs(plan, inner, junc, cores64, range(len(shapes)), TOL[dtype])
+    if dtype == "bf16":
+        # arithmetic only: against the oracle on the values the GPU holds
+        _check_pairs(plan, inner, junc, seen, range(len(shapes)), ARITH_BF16.get(batch_mode, ARITH_BF16_DEFAULT))
     # the per-pair launch loop meets the same bar
     inner2, junc2 = plan.run(plain=True)
     _check_pairs(plan, to_np(inner2), junc2, cores64, range(len(shapes)), TOL[dtype])
@@ -91,6 +112,7 @@ def test_batch_integer_cores_exact(ttc, batch_mode):
 
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
 def test_batch4096_sampled(ttc, dtype, batch_mode):
+    _skip_f32_only_bf16(batch_mode, dtype)
     import torch
     shapes = C.batch_pair_shapes(C.SEED_BATCH, 4096)
     td = torch.float32 if dtype == "f32" else torch.bfloat16
