@@ -78,6 +78,18 @@ __device__ __forceinline__ uint2 keep4(int e0, int K) {
 __device__ __forceinline__ uint2 and2(const uint2& v, const uint2& m) { return make_uint2(v.x & m.x, v.y & m.y); }
 __device__ __forceinline__ uint4 cat2(const uint2& a, const uint2& b) { return make_uint4(a.x, a.y, b.x, b.y); }
 
+typedef unsigned u32x3 __attribute__((ext_vector_type(3)));
+
+// Three dwords of a core at a dword-aligned byte offset (zeros past the
+// resource's end).
+__device__ __forceinline__ u32x3 raw_at(const CoreRes& c, int off) {
+  return __builtin_amdgcn_raw_buffer_load_b96(c.r, off, 0, 0);
+}
+// Four BF16 elements starting `sh` bits into the three dwords.
+__device__ __forceinline__ uint2 take_raw(const u32x3& v, int sh) {
+  return make_uint2(__builtin_amdgcn_alignbit(v[1], v[0], sh), __builtin_amdgcn_alignbit(v[2], v[1], sh));
+}
+
 // Mode indices per loop trip: the BF16 products are cheap, so every shape
 // with room in the register file takes several.
 template <int KC, int PT>
@@ -85,19 +97,30 @@ struct TripWidth16 {
   static constexpr int U = (KC + PT <= 4) ? 4 : (KC + PT <= 8) ? 2 : 1;
 };
 
+// VGPRs a trip holds for NA a-tiles and U mode indices: accumulators, the
+// G_A operands or their raw loads (not live at the same time), the G_B
+// operands and the next block's raw loads, the stage-1 tiles.
+template <int KC, int PT, int NA, int U>
+struct TripRegs {
+  static constexpr int KP = KC / 2, KT = KC & 1;
+  static constexpr int ga = NA * U * (KP * 4 + KT * 2), gar = NA * U * (KP * 6 + KT * 3);
+  static constexpr int n = NA * PT * 4 + (ga > gar ? ga : gar) + U * PT * (8 + 6 * 2) / 2 + NA * U * 8;
+};
+
 // Accumulate mode indices i = s0, s0 + S, ... into NA a-tiles (at[0], and
 // at[1] when NA == 2) of Out.  KC = pad16(Ka) / 16, PT = pad16(Nb) / 16.  A
 // loop trip covers U mode indices (those past I read zeros through empty
 // resources) and one 32-wide block q of b' (the last block is 16 wide when
-// pad16(Kb) is an odd multiple of 16).  The G_B rows of the next trip are
-// loaded at the start of a trip; the G_A rows of the next mode indices right
-// after this trip's stage-1 products, their last use.  Core entries past a
-// row's end (the next entries of the core) are masked to zero.
+// pad16(Kb) is an odd multiple of 16).  The G_A rows of the next mode
+// indices are loaded right after this trip's stage-1 products (their last
+// use) and shifted into operands at the end of the trip; the G_B rows of the
+// next block after this trip's stage-2 products, shifted into operands as
+// that block's stage 2 uses them.  Core entries past a row's end (the next
+// entries of the core) are masked to zero.
 template <int KC, int PT, int NA, int U>
 __device__ __forceinline__ void lds16_tiles(const StepOp& op, const TTC_LDS uint16_t* __restrict__ In, int lo,
                                             const int (&at)[2], int s0, int S, f32x4 (&acc0)[SW_MAXT],
                                             f32x4 (&acc1)[SW_MAXT]) {
-  typedef Raw4<bf16_t> R4;
   constexpr int KP = KC / 2, KT = KC & 1, KPA = KP > 0 ? KP : 1;
   const int lane = threadIdx.x & 63, li = lane & 15, g = lane >> 4;
   const int I = __builtin_amdgcn_readfirstlane(op.I), Ka = __builtin_amdgcn_readfirstlane(op.Ka),
@@ -105,12 +128,18 @@ __device__ __forceinline__ void lds16_tiles(const StepOp& op, const TTC_LDS uint
   const int QT = (Kb + 15) >> 4, QB = (QT + 1) >> 1;
   const int ip = lds16_pitch(Ka);
   const long ta = (long)op.Ma * I * Ka, tb = (long)op.Nb * I * Kb;
-  int aoff[NA];
+  // Per-lane byte offsets of the core rows, split into a dword-aligned part
+  // and the row's 2-byte parity (the same for every chunk and tile of the
+  // lane); a resource adds its own parity `adj`, and the sum picks the dword
+  // to load and the funnel shift (see raw_at / take_raw).
+  int aal[NA];
 #pragma unroll
-  for (int t = 0; t < NA; ++t) aoff[t] = (at[t] * 16 + li) * I * Ka * 2;
-  int boff[PT];
+  for (int t = 0; t < NA; ++t) aal[t] = ((at[t] * 16 + li) * I * Ka * 2) & ~3;
+  const int apar = ((li * I * Ka) & 1) << 1;
+  int bal[PT];
 #pragma unroll
-  for (int pt = 0; pt < PT; ++pt) boff[pt] = ((pt * 16 + li) * I * Kb + 4 * g) * 2;
+  for (int pt = 0; pt < PT; ++pt) bal[pt] = (((pt * 16 + li) * I * Kb + 4 * g) * 2) & ~3;
+  const int bpar = ((li * I * Kb) & 1) << 1;
   // masks of the last chunk along a' when it is partial
   const bool apart = (Ka & 15) != 0;
   const uint2 ma0 = KT ? keep4(32 * KP + 4 * g, Ka) : keep4(32 * (KP - 1) + 8 * g, Ka);
@@ -118,25 +147,46 @@ __device__ __forceinline__ void lds16_tiles(const StepOp& op, const TTC_LDS uint
   if (s0 >= I) return;
   const int step = U * S;
 
+  // Loads keep the raw dwords; the funnel shift happens when the operands
+  // are taken, so no load is waited for inside the (conditional) code that
+  // issues it.
   uint4 ga[NA][U][KPA];
   uint2 gat[NA][U];
-  uint2 gb0[U][PT], gb1[U][PT];  // current block: b' = 32q + 4g + j and 32q + 16 + 4g + j
-  uint2 gn0[U][PT], gn1[U][PT];  // next block as loaded
+  u32x3 gar[NA][U][KPA][2], gatr[NA][U];
+  int sha[U];
+  // G_B rows of the current block, raw: b' = 32q + 4g + j and 32q + 16 + 4g + j
+  u32x3 gr0[U][PT], gr1[U][PT];
+  int shb[U];
 
   auto load_a = [&](int i0) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const CoreRes ra = core_rsrc_if(i0 + u * S < I, op.ga, (long)(i0 + u * S) * Ka, ta, 2);
+      const int corr = (apar & ra.adj) << 1;
+      sha[u] = (apar ^ ra.adj) << 3;
+#pragma unroll
+      for (int t = 0; t < NA; ++t) {
+        const int o = aal[t] + corr;
+#pragma unroll
+        for (int c = 0; c < KP; ++c) {
+          gar[t][u][c][0] = raw_at(ra, o + (32 * c + 8 * g) * 2);
+          gar[t][u][c][1] = raw_at(ra, o + (32 * c + 8 * g + 4) * 2);
+        }
+        if constexpr (KT) gatr[t][u] = raw_at(ra, o + (32 * KP + 4 * g) * 2);
+      }
+    }
+  };
+  // the loaded G_A rows as operands, masked past the row ends
+  auto take_a = [&]() {
+#pragma unroll
+    for (int u = 0; u < U; ++u)
 #pragma unroll
       for (int t = 0; t < NA; ++t) {
 #pragma unroll
         for (int c = 0; c < KP; ++c)
-          ga[t][u][c] = cat2(R4::load(ra, aoff[t] + (32 * c + 8 * g) * 2), R4::load(ra, aoff[t] + (32 * c + 8 * g + 4) * 2));
-        if constexpr (KT) gat[t][u] = R4::load(ra, aoff[t] + (32 * KP + 4 * g) * 2);
+          ga[t][u][c] = cat2(take_raw(gar[t][u][c][0], sha[u]), take_raw(gar[t][u][c][1], sha[u]));
+        if constexpr (KT) gat[t][u] = take_raw(gatr[t][u], sha[u]);
       }
-    }
-  };
-  auto mask_a = [&]() {
     if (!apart) return;
 #pragma unroll
     for (int u = 0; u < U; ++u)
@@ -150,45 +200,25 @@ __device__ __forceinline__ void lds16_tiles(const StepOp& op, const TTC_LDS uint
         }
       }
   };
-  // G_B rows of block q for mode indices i0 + u S
+  // G_B rows of block q for mode indices i0 + u S (both halves; those past
+  // the core read zeros, the rest of a half block is never used)
   auto load_b = [&](int i0, int q) {
-    const bool full = 2 * q + 1 < QT;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const CoreRes rb = core_rsrc_if(i0 + u * S < I, op.gb, (long)(i0 + u * S) * Kb + 32 * q, tb, 2);
+      const int corr = (bpar & rb.adj) << 1;
+      shb[u] = (bpar ^ rb.adj) << 3;
 #pragma unroll
-      for (int pt = 0; pt < PT; ++pt) gn0[u][pt] = R4::load(rb, boff[pt]);
-      if (full) {
-#pragma unroll
-        for (int pt = 0; pt < PT; ++pt) gn1[u][pt] = R4::load(rb, boff[pt] + 32);
+      for (int pt = 0; pt < PT; ++pt) {
+        gr0[u][pt] = raw_at(rb, bal[pt] + corr);
+        gr1[u][pt] = raw_at(rb, bal[pt] + corr + 32);
       }
-    }
-  };
-  auto take_b = [&](int q) {
-    if (32 * q + 32 <= Kb) {
-#pragma unroll
-      for (int u = 0; u < U; ++u)
-#pragma unroll
-        for (int pt = 0; pt < PT; ++pt) {
-          gb0[u][pt] = gn0[u][pt];
-          gb1[u][pt] = gn1[u][pt];
-        }
-    } else {
-      const uint2 m0 = keep4(32 * q + 4 * g, Kb), m1 = keep4(32 * q + 16 + 4 * g, Kb);
-#pragma unroll
-      for (int u = 0; u < U; ++u)
-#pragma unroll
-        for (int pt = 0; pt < PT; ++pt) {
-          gb0[u][pt] = and2(gn0[u][pt], m0);
-          gb1[u][pt] = and2(gn1[u][pt], m1);
-        }
     }
   };
 
   load_a(s0);
   load_b(s0, 0);
-  mask_a();
-  take_b(0);
+  take_a();
   __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
   int i = s0, q = 0;
   for (;;) {
@@ -198,7 +228,6 @@ __device__ __forceinline__ void lds16_tiles(const StepOp& op, const TTC_LDS uint
       ni = i + step;
     }
     const bool more = ni < I;
-    if (more) load_b(ni, nq);
     const bool full = 2 * q + 1 < QT;
     // stage 1: S^T rows b' = 32q + 16h + (0..15) of each tile and mode index
     f32x4 st[NA][U][2];
@@ -237,7 +266,16 @@ __device__ __forceinline__ void lds16_tiles(const StepOp& op, const TTC_LDS uint
     // the next mode indices' G_A rows (this trip's stage 1 was their last use)
     const bool reload = more && nq == 0;
     if (reload) load_a(ni);
-    // stage 2: Out[a-tile, b-tile pt] += S_i[:, block q] . G_B[b-tile, i, block q]^T
+    // stage 2: Out[a-tile, b-tile pt] += S_i[:, block q] . G_B[b-tile, i, block q]^T,
+    // the G_B operands shifted out of the raw loads (masked past Kb in a last
+    // partial block)
+    const bool bpart = 32 * q + 32 > Kb;
+    const uint2 m0 = keep4(32 * q + 4 * g, Kb), m1 = keep4(32 * q + 16 + 4 * g, Kb);
+    auto gbop = [&](int u, int pt, bool second) -> uint2 {
+      uint2 v = take_raw(second ? gr1[u][pt] : gr0[u][pt], shb[u]);
+      if (bpart) v = and2(v, second ? m1 : m0);
+      return v;
+    };
 #pragma unroll
     for (int t = 0; t < NA; ++t)
 #pragma unroll
@@ -251,7 +289,7 @@ __device__ __forceinline__ void lds16_tiles(const StepOp& op, const TTC_LDS uint
           const uint4 sh = make_uint4(h0, h1, h2, h3), sl = make_uint4(l0, l1, l2, l3);
 #pragma unroll
           for (int pt = 0; pt < PT; ++pt) {
-            const uint4 b = cat2(gb0[u][pt], gb1[u][pt]);
+            const uint4 b = cat2(gbop(u, pt, false), gbop(u, pt, true));
             f32x4& c = t == 0 ? acc0[pt] : acc1[pt];
             c = mfma_b32(sh, b, c);
             c = mfma_b32(sl, b, c);
@@ -264,27 +302,31 @@ __device__ __forceinline__ void lds16_tiles(const StepOp& op, const TTC_LDS uint
 #pragma unroll
           for (int pt = 0; pt < PT; ++pt) {
             f32x4& c = t == 0 ? acc0[pt] : acc1[pt];
-            c = mfma_b32h(sh, gb0[u][pt], c);
-            c = mfma_b32h(sl, gb0[u][pt], c);
+            const uint2 b = gbop(u, pt, false);
+            c = mfma_b32h(sh, b, c);
+            c = mfma_b32h(sl, b, c);
           }
         }
       }
     if (!more) break;
-    take_b(nq);
-    if (reload) mask_a();
+    // the next block's G_B rows: their latency is covered by its stage 1
+    load_b(ni, nq);
+    if (reload) take_a();
     i = ni;
     q = nq;
   }
 }
 
-// NA = 2 only where one mode index per trip fits the registers; otherwise
-// the two a-tiles one after the other.  With na == 1 only acc0 is written.
+// NA = 2 only where one mode index per trip takes few enough registers;
+// otherwise the two a-tiles one after the other.  With na == 1 only acc0 is
+// written.
 template <int KC, int PT>
 __device__ __forceinline__ void lds16_tiles_u(const StepOp& op, const TTC_LDS uint16_t* In, int lo, int na,
                                               const int (&at)[2], int s0, int S, f32x4 (&acc0)[SW_MAXT],
                                               f32x4 (&acc1)[SW_MAXT]) {
   constexpr int U = TripWidth16<KC, PT>::U;
-  if constexpr (U == 1) {
+  // (the rest of the 256 registers: offsets, masks, addresses, temporaries)
+  if constexpr (U == 1 && TripRegs<KC, PT, 2, 1>::n <= 200) {
     if (na == 2) {
       lds16_tiles<KC, PT, 2, 1>(op, In, lo, at, s0, S, acc0, acc1);
       return;
