@@ -94,7 +94,7 @@ __device__ __forceinline__ uint2 take_raw(const u32x3& v, int sh) {
 // with room in the register file takes several.
 template <int KC, int PT>
 struct TripWidth16 {
-  static constexpr int U = (KC + PT <= 4) ? 4 : (KC + PT <= 8) ? 2 : 1;
+  static constexpr int U = (KC + PT <= 4) ? 4 : (KC + PT <= 6) ? 2 : 1;
 };
 
 // VGPRs a trip holds for NA a-tiles and U mode indices: accumulators, the
@@ -325,8 +325,10 @@ __device__ __forceinline__ void lds16_tiles_u(const StepOp& op, const TTC_LDS ui
                                               const int (&at)[2], int s0, int S, f32x4 (&acc0)[SW_MAXT],
                                               f32x4 (&acc1)[SW_MAXT]) {
   constexpr int U = TripWidth16<KC, PT>::U;
-  // (the rest of the 256 registers: offsets, masks, addresses, temporaries)
-  if constexpr (U == 1 && TripRegs<KC, PT, 2, 1>::n <= 200) {
+  // (the rest of the 256 registers: offsets, masks, addresses, temporaries
+  // and what the step keeps live around the call; a larger bound spilled in
+  // the loop and measured slower on the 4096-pair batch)
+  if constexpr (U == 1 && TripRegs<KC, PT, 2, 1>::n <= 160) {
     if (na == 2) {
       lds16_tiles<KC, PT, 2, 1>(op, In, lo, at, s0, S, acc0, acc1);
       return;
