@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--parts", default="pair10,mpo8,batch,layer4")
     ap.add_argument("--no-beside", action="store_true",
                     help="skip the measurements beside the step (BF16 batch, plain loop, BF16 layer)")
+    ap.add_argument("--batch-dtype", default="f32", choices=["f32", "bf16"],
+                    help="core dtype of the batch part (bf16: the BF16 schedule as the timed part, for profiling it)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB mebibytes five times (counter calibration)")
     return ap.parse_args()
@@ -78,7 +80,7 @@ def recorded_traffic(kernel):
 
 
 # ------------------------------------------------------------- workload setup
-def setup(parts):
+def setup(parts, batch_dtype="f32"):
     import torch
 
     import paper_2109_00626_amd as ttc
@@ -98,7 +100,7 @@ def setup(parts):
                          v=C.gen_tt_torch(C.SEED_MPO8, 2, sv, dev, torch.bfloat16), sw=sw, sv=sv)
     if "batch" in parts:
         shapes = C.batch_pair_shapes(C.SEED_BATCH, 4096)
-        pairs = C.gen_batch_torch(C.SEED_BATCH, shapes, dev, torch.float32)
+        pairs = C.gen_batch_torch(C.SEED_BATCH, shapes, dev, torch.bfloat16 if batch_dtype == "bf16" else torch.float32)
         plan = ttc.BatchPlan(pairs)
         inner, junc = plan.outputs()
         W["batch"] = dict(shapes=shapes, pairs=pairs, plan=plan, inner=inner, junc=junc)
@@ -305,7 +307,7 @@ def main():
     import paper_2109_00626_amd as ttc
 
     parts = [p for p in args.parts.split(",") if p]
-    W = setup(parts)
+    W = setup(parts, args.batch_dtype)
     stream = torch.cuda.current_stream()
     for _ in range(args.warmup):
         for p in parts:
@@ -363,11 +365,11 @@ def main():
         ms = part_ms["batch"]
         ach = alg["batch"]["bytes"] / (ms * 1e-3) / 1e9
         cfg = W["batch"]["plan"].config
-        kname = {"lds": "batch_lds_kernel", "lds1": "batch_lds_kernel_inplace", "persistent": "batch_kernel",
-                 "levels": "level_kernel"}[cfg["mode"]]
+        kname = {"lds": "batch_lds_kernel", "lds1": "batch_lds_kernel_inplace", "lds1b": "batch_lds_kernel_b16",
+                 "persistent": "batch_kernel", "levels": "level_kernel"}[cfg["mode"]]
         roof = {"bound": "hbm", "kernel": kname, "schedule": cfg, "achieved": round(ach, 1),
                 "peak": PEAK["hbm_GBs"], "unit": "GB/s", "frac": round(ach / PEAK["hbm_GBs"], 4),
-                "traffic": recorded_traffic(f"{kname}/{cfg['threads']}") if cfg["mode"] in ("lds", "lds1") else None,
+                "traffic": recorded_traffic(f"{kname}/{cfg['threads']}") if cfg["mode"] in ("lds", "lds1", "lds1b") else None,
                 "per_launch": "all 4096 pairs: every core read once, 4096 FP64 scalars and the junctions written"}
     else:
         ms = part_ms[dominant]
@@ -376,7 +378,7 @@ def main():
                 "unit": "GB/s", "frac": round(ach / PEAK["hbm_GBs"], 4), "traffic": None}
 
     beside = {}
-    if "batch" in parts and not args.no_beside:
+    if "batch" in parts and not args.no_beside and args.batch_dtype == "f32":
         d = W["batch"]
         plan = d["plan"]
 
@@ -406,7 +408,9 @@ def main():
         beside["batch_bf16"] = {"batched_ms": round(bf_ms, 4),
                                 "contractions_per_s": round(8192 / (bf_ms * 1e-3), 1),
                                 "GBs": round(plan_bf.bytes / (bf_ms * 1e-3) / 1e9, 1),
-                                "algorithmic_GB": round(plan_bf.bytes / 1e9, 3)}
+                                "TFLOPs": round(plan_bf.flops / (bf_ms * 1e-3) / 1e12, 3),
+                                "algorithmic_GB": round(plan_bf.bytes / 1e9, 3),
+                                "schedule": plan_bf.config}
         del pairs_bf, plan_bf, ib, jb
     if "layer4" in parts and not args.no_beside:
         d = W["layer4"]
@@ -467,9 +471,9 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 (mpo8: bf16 in, f32 acc)",
+        "dtype": "f32 (mpo8: bf16 in, f32 acc)" if args.batch_dtype == "f32" else "f32 (mpo8, batch: bf16 in, f32 acc)",
         "data": "synthetic (seeded generator; shapes and distributions of the five workloads)",
-        "config": {"workload": "tt-hot-path: " + "+".join(parts),
+        "config": {"workload": "tt-hot-path: " + "+".join(parts) + (" (batch with BF16 cores)" if args.batch_dtype == "bf16" else ""),
                    "contractions_per_step": {p: CONTRACTIONS[p] for p in parts},
                    "parallelism": "single GPU"},
         "roofline": roof,
