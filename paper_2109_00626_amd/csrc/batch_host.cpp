@@ -82,6 +82,7 @@ struct ttc_plan {
   int mode = 0;                // 0: persistent kernel, 1: one launch per level, 2: LDS-resident persistent
                                // kernel, 3: the same with one interface buffer updated in place
   int buf_elems = 0;           // LDS-resident kernel: floats per interface buffer
+  int stage16 = 0;             // BF16-MFMA variant: G_B staged in LDS (fits two workgroups per CU)
   int levels = 0;              // max order - 1
   std::vector<int> lvl_off;    // item offsets per level (levels + 1 entries; level l at index l-1)
   int n_meet = 0;
@@ -161,6 +162,9 @@ int lds16_iface_elems_h(int R, int P) {
 
 bool lds_mode(int mode) { return mode == 2 || mode == 3 || mode == 4; }
 
+// A bound on the LDS-resident kernels' static LDS.
+constexpr int kStaticLds = 1536;
+
 int lds_variant(int mode) { return mode == 4 ? kBatchLdsB16 : mode == 3 ? kBatchLdsInPlace : kBatchLdsTwo; }
 
 // Time model of the LDS-resident kernel for one pair, in shader cycles of
@@ -239,6 +243,7 @@ BatchArgs make_args(ttc_plan* P, const int* begin, const int* order, double* inn
   a.inner = inner;
   a.junction = junc;
   a.buf_elems = P->buf_elems;
+  a.stage = P->mode == 4 ? P->stage16 : 0;
   a.npairs = P->n;
   (void)grid;
   return a;
@@ -296,6 +301,11 @@ hipError_t run_mode(ttc_plan* P, double* inner, float* junc, hipStream_t s) {
 // Largest number of LDS-resident workgroups per CU (bufs: interface buffers
 // per workgroup).
 int lds_kernel_per_cu(const ttc_plan* P, int bufs) {
+  if (bufs == 0) {
+    // BF16-MFMA variant: one interface buffer (two BF16 planes) and the stage when enabled
+    const int bytes = P->buf_elems * (int)sizeof(float) + (P->stage16 ? kBatchStageBytes : 0) + kStaticLds;
+    return std::max(1, std::min(2, (160 * 1024) / bytes));
+  }
   const int bytes = bufs * P->buf_elems * (int)sizeof(float) + 4 * 1024;
   return std::max(1, std::min(2, (160 * 1024) / bytes));
 }
@@ -383,7 +393,7 @@ ttc_status autotune(ttc_plan* P) {
   }
   std::vector<LaunchCfg> cands;
   if (P->dt == TTC_BF16 && (want < 0 || want == 4))
-    for (int pc = 1; pc <= lds_kernel_per_cu(P, 1); ++pc) cands.push_back({4, 256, pc});
+    for (int pc = 1; pc <= lds_kernel_per_cu(P, 0); ++pc) cands.push_back({4, 256, pc});
   if (want < 0 || want == 3)
     for (int pc = 1; pc <= lds_kernel_per_cu(P, 1); ++pc) cands.push_back({3, 256, pc});
   if (want < 0 || want == 2) {
@@ -509,6 +519,8 @@ ttc_status tt_batch_plan_create(const ttc_pair* pairs, int32_t n, uint32_t ops, 
     }
   }
   P->buf_elems = (P->buf_elems + 7) & ~7;  // BF16 lo plane at a 16-byte boundary
+  // the BF16-MFMA variant stages G_B in LDS when two workgroups per CU still fit
+  P->stage16 = (dt == TTC_BF16 && 2 * (P->buf_elems * 4 + kBatchStageBytes + kStaticLds) <= 160 * 1024) ? 1 : 0;
   hipError_t e = hipGetDevice(&P->device);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&P->cus, hipDeviceAttributeMultiprocessorCount, P->device);
   if (e != hipSuccess) {
@@ -573,7 +585,7 @@ ttc_status tt_batch_plan_create(const ttc_pair* pairs, int32_t n, uint32_t ops, 
   cp(P->d_claim, zz, sizeof(zz));
   if (st == TTC_OK) {
     hipError_t ee = batch_set_lds(kLdsBytes);
-    if (ee == hipSuccess) ee = batch_lds_set_lds(2 * P->buf_elems * (int)sizeof(float));
+    if (ee == hipSuccess) ee = batch_lds_set_lds(2 * P->buf_elems * (int)sizeof(float), P->stage16 ? kBatchStageBytes : 0);
     if (ee != hipSuccess) st = fail(TTC_ERR_HIP, std::string("kernel attribute: ") + hipGetErrorString(ee));
   }
   // level-by-level tables: items (pair, 16-row tile) of every level, heavy first

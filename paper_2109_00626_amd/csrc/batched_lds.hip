@@ -106,7 +106,7 @@ __global__ __launch_bounds__(NT, ONE ? 2 : 1) void batch_lds_kernel(BatchArgs a)
         op.Nb = sy.ranks[k];
         op.Kb = sy.ranks[k + 1];
       }
-      if constexpr (M16) lds16_step_inplace<NW>(op, pl, lo, yf == yf_next);
+      if constexpr (M16) lds16_step_inplace<NW>(op, pl, lo, yf == yf_next, a.stage ? pl + 2 * lo : nullptr);
       else if constexpr (ONE) lds_step_inplace<Tin, NW>(op, in, yf == yf_next);
       else lds_step<Tin, NW>(op, in, out, yf == yf_next);
       if (k == N - 2 && (a.ops & TTC_OP_SUFFIX2)) {
@@ -158,7 +158,7 @@ __global__ __launch_bounds__(NT, ONE ? 2 : 1) void batch_lds_kernel(BatchArgs a)
   }
 }
 
-hipError_t batch_lds_set_lds(int bytes) {
+hipError_t batch_lds_set_lds(int bytes, int stage_bytes) {
   // bytes: two interface buffers; the in-place kernels take half
   const void* two[] = {reinterpret_cast<const void*>(&batch_lds_kernel<float, 256, false>),
                        reinterpret_cast<const void*>(&batch_lds_kernel<float, 512, false>),
@@ -169,19 +169,19 @@ hipError_t batch_lds_set_lds(int bytes) {
     if (e != hipSuccess) return e;
   }
   const void* one[] = {reinterpret_cast<const void*>(&batch_lds_kernel<float, 256, true>),
-                       reinterpret_cast<const void*>(&batch_lds_kernel<bf16_t, 256, true>),
-                       reinterpret_cast<const void*>(&batch_lds_kernel<bf16_t, 256, true, true>)};
+                       reinterpret_cast<const void*>(&batch_lds_kernel<bf16_t, 256, true>)};
   for (const void* k : one) {
     hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes / 2);
     if (e != hipSuccess) return e;
   }
-  return hipSuccess;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&batch_lds_kernel<bf16_t, 256, true, true>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes / 2 + stage_bytes);
 }
 
 hipError_t launch_batch_lds(ttc_dtype dt, const BatchArgs& a, int grid, int threads, int variant, hipStream_t s) {
   if (variant == kBatchLdsB16) {
     if (dt != TTC_BF16) return hipErrorInvalidValue;
-    const size_t lds = (size_t)a.buf_elems * sizeof(float);
+    const size_t lds = (size_t)a.buf_elems * sizeof(float) + (a.stage ? kBatchStageBytes : 0);
     hipLaunchKernelGGL((batch_lds_kernel<bf16_t, 256, true, true>), dim3(grid), dim3(256), lds, s, a);
     return hipGetLastError();
   }

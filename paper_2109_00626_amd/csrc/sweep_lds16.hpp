@@ -32,6 +32,10 @@
 #pragma once
 #include "sweep_lds.hpp"
 
+#ifndef STAGED_MAX_REGS
+#define STAGED_MAX_REGS 160  // register budget of a staged trip (see StagedRegs); larger staged shapes spilled and ran slower
+#endif
+
 namespace ttc {
 
 __host__ __device__ __forceinline__ int lds16_pitch(int n) { return pad16(n) + 8; }
@@ -79,6 +83,7 @@ __device__ __forceinline__ uint2 and2(const uint2& v, const uint2& m) { return m
 __device__ __forceinline__ uint4 cat2(const uint2& a, const uint2& b) { return make_uint4(a.x, a.y, b.x, b.y); }
 
 typedef unsigned u32x3 __attribute__((ext_vector_type(3)));
+typedef unsigned u32x4_t __attribute__((ext_vector_type(4)));
 
 // Three dwords of a core at a dword-aligned byte offset (zeros past the
 // resource's end).
@@ -373,6 +378,259 @@ __device__ __forceinline__ void lds16_tiles_v(const StepOp& op, const TTC_LDS ui
   }
 }
 
+// Row pitch (BF16 elements) of the LDS stage that holds one 32-wide block
+// of G_B: a byte stride of 16 x 5, so 16 lanes reading 16 bytes from 16
+// consecutive rows touch disjoint banks.
+constexpr int kStagePitch = 40;
+
+__device__ __forceinline__ u32x4_t raw4_at(const CoreRes& c, int off) {
+  return __builtin_amdgcn_raw_buffer_load_b128(c.r, off, 0, 0);
+}
+
+// The step of lds16_tiles for shapes where every wave walks all mode indices
+// (no mode-index split) and G_B is wide: each trip's G_B block is loaded once
+// by the whole workgroup instead of by every wave.  Thread t loads row t / 2
+// of the block (sixteen b' from 16 (t % 2), with aligned 16-byte loads and a
+// funnel shift), masks entries past Kb and writes them to the LDS stage in
+// the order of the stage-2 operands (position 8g + j of a row holds the b'
+// that lane group g puts in slot j); waves read their operands from there.
+// A trip: stage 1 (In^T, G_A), the next G_A rows if a mode index ends,
+// barrier (the stage is free), stage write, loads of the next block,
+// barrier (the stage is full), stage 2.  Every wave of the workgroup calls
+// this with the same step (na = 0, 1 or 2 output row tiles of its own), so
+// the barriers match.
+template <int KC, int PT, int NT>
+__device__ __forceinline__ void lds16_tiles_staged(const StepOp& op, const TTC_LDS uint16_t* __restrict__ In, int lo,
+                                                   TTC_LDS uint16_t* __restrict__ stage, int na, const int (&at)[2],
+                                                   f32x4 (&acc0)[SW_MAXT], f32x4 (&acc1)[SW_MAXT]) {
+  static_assert(NT >= 2 * 16 * PT, "one staging thread per half row");
+  constexpr int KP = KC / 2, KT = KC & 1, KPA = KP > 0 ? KP : 1;
+  const int lane = threadIdx.x & 63, li = lane & 15, g = lane >> 4;
+  const int I = __builtin_amdgcn_readfirstlane(op.I), Ka = __builtin_amdgcn_readfirstlane(op.Ka),
+            Kb = __builtin_amdgcn_readfirstlane(op.Kb);
+  const int QT = (Kb + 15) >> 4, QB = (QT + 1) >> 1;
+  const int ip = lds16_pitch(Ka);
+  const long ta = (long)op.Ma * I * Ka, tb = (long)op.Nb * I * Kb;
+  int aal[2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t) aal[t] = ((at[t] * 16 + li) * I * Ka * 2) & ~3;
+  const int apar = ((li * I * Ka) & 1) << 1;
+  const bool apart = (Ka & 15) != 0;
+  const uint2 ma0 = KT ? keep4(32 * KP + 4 * g, Ka) : keep4(32 * (KP - 1) + 8 * g, Ka);
+  const uint2 ma1 = keep4(32 * (KP - 1) + 8 * g + 4, Ka);
+  // staging: row sr of the block, elements 16 sh2 .. 16 sh2 + 15
+  const int sr = threadIdx.x >> 1, sh2 = threadIdx.x & 1;
+  const bool srow = sr < 16 * PT;
+  const int srel = (sr * I * Kb + 16 * sh2) * 2;
+  const int sal = srel & ~3, spar = srel & 2;
+
+  uint4 ga[2][KPA];
+  uint2 gat[2];
+  u32x3 gar[2][KPA][2], gatr[2];
+  int sha = 0;
+  u32x4_t sr0, sr1;
+  unsigned sr2 = 0;
+  int shs = 0;
+
+  auto load_a = [&](int i0) {
+    const CoreRes ra = core_rsrc(op.ga, (long)i0 * Ka, ta, 2);
+    const int corr = (apar & ra.adj) << 1;
+    sha = (apar ^ ra.adj) << 3;
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      if (t >= na) break;
+      const int o = aal[t] + corr;
+#pragma unroll
+      for (int c = 0; c < KP; ++c) {
+        gar[t][c][0] = raw_at(ra, o + (32 * c + 8 * g) * 2);
+        gar[t][c][1] = raw_at(ra, o + (32 * c + 8 * g + 4) * 2);
+      }
+      if constexpr (KT) gatr[t] = raw_at(ra, o + (32 * KP + 4 * g) * 2);
+    }
+  };
+  auto take_a = [&]() {
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      if (t >= na) break;
+#pragma unroll
+      for (int c = 0; c < KP; ++c) ga[t][c] = cat2(take_raw(gar[t][c][0], sha), take_raw(gar[t][c][1], sha));
+      if constexpr (KT) gat[t] = take_raw(gatr[t], sha);
+      if (apart) {
+        if constexpr (KT) {
+          gat[t] = and2(gat[t], ma0);
+        } else {
+          uint4& v = ga[t][KP - 1];
+          v = make_uint4(v.x & ma0.x, v.y & ma0.y, v.z & ma1.x, v.w & ma1.y);
+        }
+      }
+    }
+  };
+  // raw loads of this thread's part of block q of mode index i0
+  auto load_s = [&](int i0, int q) {
+    if (!srow) return;
+    const CoreRes rb = core_rsrc(op.gb, (long)i0 * Kb + 32 * q, tb, 2);
+    const int o = sal + ((spar & rb.adj) << 1);
+    shs = (spar ^ rb.adj) << 3;
+    sr0 = raw4_at(rb, o);
+    sr1 = raw4_at(rb, o + 16);
+    sr2 = __builtin_amdgcn_raw_buffer_load_b32(rb.r, o + 32, 0, 0);
+  };
+  // the loaded part of block q, masked past Kb, into the stage
+  auto write_s = [&](int q) {
+    if (!srow) return;
+    const unsigned w[9] = {sr0[0], sr0[1], sr0[2], sr0[3], sr1[0], sr1[1], sr1[2], sr1[3], sr2};
+    const int e0 = 32 * q + 16 * sh2;
+    TTC_LDS uint16_t* row = stage + sr * kStagePitch;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      uint2 v = make_uint2(__builtin_amdgcn_alignbit(w[2 * m + 1], w[2 * m], shs),
+                           __builtin_amdgcn_alignbit(w[2 * m + 2], w[2 * m + 1], shs));
+      if (e0 + 4 * m + 4 > Kb) v = and2(v, keep4(e0 + 4 * m, Kb));
+      const int hh = 4 * sh2 + m;
+      const int pos = hh < 4 ? 8 * hh : 8 * (hh - 4) + 4;
+      *reinterpret_cast<TTC_LDS uint2*>(row + pos) = v;
+    }
+  };
+
+  load_a(0);
+  load_s(0, 0);
+  take_a();
+  int i = 0, q = 0;
+  for (;;) {
+    int ni = i, nq = q + 1;
+    if (nq == QB) {
+      nq = 0;
+      ni = i + 1;
+    }
+    const bool more = ni < I;
+    const bool full = 2 * q + 1 < QT;
+    // stage 1: S^T rows b' = 32q + 16h + (0..15) of each of the wave's tiles
+    f32x4 st[2][2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if (h == 1 && !full) break;
+      const TTC_LDS uint16_t* row = In + (32 * q + 16 * h + li) * ip;
+#pragma unroll
+      for (int t = 0; t < 2; ++t) st[t][h] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int c = 0; c < KP; ++c) {
+        const uint4 vh = *reinterpret_cast<const TTC_LDS uint4*>(row + 32 * c + 8 * g);
+        const uint4 vl = *reinterpret_cast<const TTC_LDS uint4*>(row + lo + 32 * c + 8 * g);
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          if (t >= na) break;
+          st[t][h] = mfma_b32(vh, ga[t][c], st[t][h]);
+          st[t][h] = mfma_b32(vl, ga[t][c], st[t][h]);
+        }
+      }
+      if constexpr (KT) {
+        const uint2 vh = *reinterpret_cast<const TTC_LDS uint2*>(row + 32 * KP + 4 * g);
+        const uint2 vl = *reinterpret_cast<const TTC_LDS uint2*>(row + lo + 32 * KP + 4 * g);
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          if (t >= na) break;
+          st[t][h] = mfma_b32h(vh, gat[t], st[t][h]);
+          st[t][h] = mfma_b32h(vl, gat[t], st[t][h]);
+        }
+      }
+    }
+    const bool reload = more && nq == 0;
+    if (reload) load_a(ni);
+    __syncthreads();  // every wave is done with the stage's previous block
+    write_s(q);
+    if (more) load_s(ni, nq);
+    __syncthreads();  // the stage holds block q
+    // stage 2 with the G_B operands from the stage
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      if (t >= na) break;
+      if (full) {
+        unsigned h0, l0, h1, l1, h2, l2, h3, l3;
+        split2(st[t][0][0], st[t][0][1], h0, l0);
+        split2(st[t][0][2], st[t][0][3], h1, l1);
+        split2(st[t][1][0], st[t][1][1], h2, l2);
+        split2(st[t][1][2], st[t][1][3], h3, l3);
+        const uint4 sh = make_uint4(h0, h1, h2, h3), sl = make_uint4(l0, l1, l2, l3);
+#pragma unroll
+        for (int pt = 0; pt < PT; ++pt) {
+          const uint4 b = *reinterpret_cast<const TTC_LDS uint4*>(stage + (pt * 16 + li) * kStagePitch + 8 * g);
+          f32x4& c = t == 0 ? acc0[pt] : acc1[pt];
+          c = mfma_b32(sh, b, c);
+          c = mfma_b32(sl, b, c);
+        }
+      } else {
+        unsigned h0, l0, h1, l1;
+        split2(st[t][0][0], st[t][0][1], h0, l0);
+        split2(st[t][0][2], st[t][0][3], h1, l1);
+        const uint2 sh = make_uint2(h0, h1), sl = make_uint2(l0, l1);
+#pragma unroll
+        for (int pt = 0; pt < PT; ++pt) {
+          const uint2 b = *reinterpret_cast<const TTC_LDS uint2*>(stage + (pt * 16 + li) * kStagePitch + 8 * g);
+          f32x4& c = t == 0 ? acc0[pt] : acc1[pt];
+          c = mfma_b32h(sh, b, c);
+          c = mfma_b32h(sl, b, c);
+        }
+      }
+    }
+    if (!more) break;
+    if (reload) take_a();
+    i = ni;
+    q = nq;
+  }
+}
+
+// VGPRs of a staged trip: both output tiles, the G_A operands and their raw
+// reload (live together: the operands carry over to the next block), the
+// stage-1 tiles, the staging thread's raw dwords.
+template <int KC, int PT>
+struct StagedRegs {
+  static constexpr int KP = KC / 2, KT = KC & 1;
+  static constexpr int n = 2 * PT * 4 + 2 * (KP * 4 + KT * 2) + 2 * (KP * 6 + KT * 3) + 16 + 9;
+};
+
+template <int KC, int PT, int NT>
+__device__ __forceinline__ void lds16_staged_t(const StepOp& op, const TTC_LDS uint16_t* In, int lo,
+                                               TTC_LDS uint16_t* stage, int na, const int (&at)[2],
+                                               f32x4 (&acc0)[SW_MAXT], f32x4 (&acc1)[SW_MAXT]) {
+  if constexpr (StagedRegs<KC, PT>::n <= STAGED_MAX_REGS) {
+    lds16_tiles_staged<KC, PT, NT>(op, In, lo, stage, na, at, acc0, acc1);
+  } else {
+    // too many registers for a staged trip: each wave streams its own G_B
+    if (na > 0) lds16_tiles_u<KC, PT>(op, In, lo, na, at, 0, 1, acc0, acc1);
+  }
+}
+
+template <int KC, int NT>
+__device__ __forceinline__ void lds16_staged_p(const StepOp& op, const TTC_LDS uint16_t* In, int lo,
+                                               TTC_LDS uint16_t* stage, int na, const int (&at)[2],
+                                               f32x4 (&acc0)[SW_MAXT], f32x4 (&acc1)[SW_MAXT]) {
+  switch ((op.Nb + 15) >> 4) {
+    case 3: lds16_staged_t<KC, 3, NT>(op, In, lo, stage, na, at, acc0, acc1); break;
+    case 4: lds16_staged_t<KC, 4, NT>(op, In, lo, stage, na, at, acc0, acc1); break;
+    case 5: lds16_staged_t<KC, 5, NT>(op, In, lo, stage, na, at, acc0, acc1); break;
+    case 6: lds16_staged_t<KC, 6, NT>(op, In, lo, stage, na, at, acc0, acc1); break;
+    case 7: lds16_staged_t<KC, 7, NT>(op, In, lo, stage, na, at, acc0, acc1); break;
+    default: lds16_staged_t<KC, 8, NT>(op, In, lo, stage, na, at, acc0, acc1); break;
+  }
+}
+
+// The staged step for pad16(Nb) >= 48 (na output row tiles of this wave).
+template <int NT>
+__device__ __forceinline__ void lds16_staged_v(const StepOp& op, const TTC_LDS uint16_t* In, int lo,
+                                               TTC_LDS uint16_t* stage, int na, const int (&at)[2],
+                                               f32x4 (&acc0)[SW_MAXT], f32x4 (&acc1)[SW_MAXT]) {
+  switch ((op.Ka + 15) >> 4) {
+    case 1: lds16_staged_p<1, NT>(op, In, lo, stage, na, at, acc0, acc1); break;
+    case 2: lds16_staged_p<2, NT>(op, In, lo, stage, na, at, acc0, acc1); break;
+    case 3: lds16_staged_p<3, NT>(op, In, lo, stage, na, at, acc0, acc1); break;
+    case 4: lds16_staged_p<4, NT>(op, In, lo, stage, na, at, acc0, acc1); break;
+    case 5: lds16_staged_p<5, NT>(op, In, lo, stage, na, at, acc0, acc1); break;
+    case 6: lds16_staged_p<6, NT>(op, In, lo, stage, na, at, acc0, acc1); break;
+    case 7: lds16_staged_p<7, NT>(op, In, lo, stage, na, at, acc0, acc1); break;
+    default: lds16_staged_p<8, NT>(op, In, lo, stage, na, at, acc0, acc1); break;
+  }
+}
+
 // Store (FIRST) or add the a-tile `at` of Out into the two planes: acc[pt][v]
 // is Out[at*16 + 4g + v, pt*16 + li].  native: Out^T layout (rows b, pitch
 // lds16_pitch(Ma)), one 8-byte write per plane and tile; else Out layout
@@ -432,9 +690,11 @@ __device__ __forceinline__ void lds16_put(TTC_LDS uint16_t* Out, int lo, bool na
 // The in-place step (see lds_step_inplace) on the BF16 planes: each wave
 // keeps at most two output tiles in registers until every wave has read In,
 // then the tiles overwrite it in the fixed order of their mode-index parts.
-// Ends with a workgroup barrier.
+// `stage` (kStagePitch x 128 BF16, or null) lets steps with wide G_B and no
+// mode-index split stage G_B in LDS.  Ends with a workgroup barrier.
 template <int NW>
-__device__ __forceinline__ void lds16_step_inplace(const StepOp& op, TTC_LDS uint16_t* Buf, int lo, bool native) {
+__device__ __forceinline__ void lds16_step_inplace(const StepOp& op, TTC_LDS uint16_t* Buf, int lo, bool native,
+                                                   TTC_LDS uint16_t* stage) {
   const int RT = (op.Ma + 15) >> 4;  // <= 8 <= 2 NW
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   int S = 1, best = ((RT + NW - 1) / NW) * op.I;
@@ -450,7 +710,12 @@ __device__ __forceinline__ void lds16_step_inplace(const StepOp& op, TTC_LDS uin
   f32x4 keep[SW_MAXT], acc[SW_MAXT];
 #pragma unroll
   for (int t = 0; t < SW_MAXT; ++t) keep[t] = acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-  if (S == 1 && item1 < items) {
+  if (S == 1 && stage && op.Nb > 32) {
+    // wide G_B, every wave on all mode indices: the workgroup stages G_B
+    const int na = (item0 < items) + (item1 < items);
+    const int at[2] = {item0, item1};
+    lds16_staged_v<NW * 64>(op, Buf, lo, stage, na, at, keep, acc);
+  } else if (S == 1 && item1 < items) {
     // both of the wave's a-tiles, every mode index
     const int at[2] = {item0, item1};
     lds16_tiles_v(op, Buf, lo, 2, at, 0, 1, keep, acc);

@@ -31,6 +31,7 @@ struct BatchArgs {
   int buf_elems;         // LDS-resident sweep: floats per interface buffer (BF16 planes: elements per plane)
   long long* clock;      // tracing (may be null): start/end clock per pair, then the workgroup
   int npairs;
+  int stage;             // BF16-MFMA variant: the dynamic LDS holds a G_B stage after the interface planes
   int* claim;            // LDS-resident kernels: when set, workgroups claim positions of `order`
                          // (all npairs of them) from claim[0] and count exits in claim[1]; both are
                          // zero at launch and the last workgroup to exit clears them
@@ -62,7 +63,10 @@ hipError_t level_set_lds(int level_bytes, int meet_bytes);
 hipError_t launch_level(ttc_dtype dt, const LevelArgs& a, int nitems, size_t lds, hipStream_t s);
 hipError_t launch_meet_level(ttc_dtype dt, const LevelArgs& a, int npairs, size_t lds, hipStream_t s);
 hipError_t launch_batch(ttc_dtype dt, const BatchArgs& a, int grid, int threads, hipStream_t s);
-hipError_t batch_lds_set_lds(int bytes);
+// bytes: two interface buffers; stage_bytes: the BF16-MFMA variant's G_B stage (0 when off)
+hipError_t batch_lds_set_lds(int bytes, int stage_bytes);
+// Bytes of that stage: 128 rows of 40 BF16 (kStagePitch in sweep_lds16.hpp).
+constexpr int kBatchStageBytes = 128 * 40 * 2;
 // LDS-resident kernel variants: two FP32 interface buffers, one FP32 buffer
 // updated in place, or (BF16 cores only) in place on BF16 MFMA with the
 // interface as BF16 hi / lo planes.
