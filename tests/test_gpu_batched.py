@@ -165,3 +165,62 @@ def test_batch_traced_run(ttc):
     for p, (sx, _) in enumerate(shapes):
         s = steps[p, :sx.order]
         assert s[0] >= clk[p, 0] and np.all(np.diff(s) >= 0) and s[-1] == clk[p, 1]
+
+
+def _abs_sweep_bound(x, y):
+    """Largest interface or per-index product of the right-to-left sweep of
+    the entrywise absolute values: a bound on every partial sum the GPU
+    forms for these cores, whatever its summation order."""
+    V, b = np.ones((1, 1)), 1.0
+    for k in range(len(x) - 1, 0, -1):
+        ax, ay = np.abs(x[k]), np.abs(y[k])
+        out = np.zeros((ax.shape[0], ay.shape[0]))
+        for i in range(ax.shape[1]):
+            b = max(b, float(np.max(ax[:, i, :] @ V)), float(np.max(V @ ay[:, i, :].T)))
+            out += ax[:, i, :] @ V @ ay[:, i, :].T
+        V = out
+        b = max(b, float(np.max(V)))
+    return b
+
+
+@pytest.mark.parametrize("mode", ["lds1b", "lds1"])
+def test_batch_bf16_odd_modes_wide_ranks(ttc, monkeypatch, mode):
+    """BF16 cores with odd mode sizes (rows starting at odd element offsets,
+    so the per-lane funnel shifts differ), ranks up to 128 and G_B wider
+    than 32 rows (the BF16-MFMA schedule stages those blocks in LDS): the
+    arithmetic-only error against the oracle on the rounded values, and
+    exact results for integer cores at the same shapes."""
+    monkeypatch.setenv("TTC_BATCH_MODE", mode)
+    specs = [([3, 5, 7], [1, 37, 43, 1], [1, 88, 27, 1]),
+             ([7, 9, 3, 5], [1, 70, 128, 33, 1], [1, 128, 65, 41, 1]),
+             ([5, 11, 7], [1, 100, 47, 1], [1, 33, 120, 1]),
+             ([9, 3, 5, 3, 7], [1, 49, 64, 96, 80, 1], [1, 50, 64, 97, 48, 1])]
+    gpu, seen = [], []
+    for p, (modes, rx, ry) in enumerate(specs):
+        xg, xs = to_gpu(C.gen_tt_np(C.SEED_BATCH, 9001 + 2 * p, C.TTShape(modes, rx)), "bf16")
+        yg, ys = to_gpu(C.gen_tt_np(C.SEED_BATCH, 9002 + 2 * p, C.TTShape(modes, ry)), "bf16")
+        gpu.append((xg, yg))
+        seen.append((xs, ys))
+    plan = ttc.BatchPlan(gpu)
+    assert plan.config["mode"] == mode
+    inner, junc = plan.run()
+    _check_pairs(plan, to_np(inner), junc, seen, range(len(specs)), ARITH_BF16.get(mode, ARITH_BF16_DEFAULT))
+    # integer cores (odd modes, G_B wider than 32 rows): every partial sum of
+    # every step is bounded by the sweep of the absolute values, which stays
+    # below 2^16, so the 16-bit interface and FP32 sums are exact
+    int_specs = [([3, 5, 7], [1, 37, 43, 1], [1, 88, 27, 1]),
+                 ([3, 3, 5], [1, 40, 50, 1], [1, 100, 36, 1]),
+                 ([3, 5, 3], [1, 128, 33, 1], [1, 70, 49, 1])]
+    gpu, want = [], []
+    for p, (modes, rx, ry) in enumerate(int_specs):
+        x = C.gen_int_tt_np(710 + p, 1, C.TTShape(modes, rx))
+        y = C.gen_int_tt_np(710 + p, 2, C.TTShape(modes, ry))
+        bound = _abs_sweep_bound(x, y)
+        assert bound < 2 ** 16, (p, bound)
+        gpu.append((to_gpu(x, "bf16")[0], to_gpu(y, "bf16")[0]))
+        want.append(_oracle_pair(x, y))
+    plan = ttc.BatchPlan(gpu)
+    inner, junc = plan.run()
+    for p, (z, K) in enumerate(want):
+        assert float(inner[p]) == z
+        assert np.array_equal(to_np(plan.junction(junc, p)), K)
