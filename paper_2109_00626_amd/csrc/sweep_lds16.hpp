@@ -32,9 +32,6 @@
 #pragma once
 #include "sweep_lds.hpp"
 
-#ifndef STAGED_MAX_REGS
-#define STAGED_MAX_REGS 160  // register budget of a staged trip (see StagedRegs); larger staged shapes spilled and ran slower
-#endif
 
 namespace ttc {
 
@@ -102,9 +99,10 @@ struct TripWidth16 {
   static constexpr int U = (KC + PT <= 4) ? 4 : (KC + PT <= 6) ? 2 : 1;
 };
 
-// VGPRs a trip holds for NA a-tiles and U mode indices: accumulators, the
-// G_A operands or their raw loads (not live at the same time), the G_B
-// operands and the next block's raw loads, the stage-1 tiles.
+// A rough count of the VGPRs a trip holds for NA a-tiles and U mode
+// indices: accumulators, the larger of the G_A operands and their raw
+// reload, the raw G_B loads with the operands shifted out of them, the
+// stage-1 tiles.  The bound it is compared with was chosen by timing.
 template <int KC, int PT, int NA, int U>
 struct TripRegs {
   static constexpr int KP = KC / 2, KT = KC & 1;
@@ -592,7 +590,8 @@ template <int KC, int PT, int NT>
 __device__ __forceinline__ void lds16_staged_t(const StepOp& op, const TTC_LDS uint16_t* In, int lo,
                                                TTC_LDS uint16_t* stage, int na, const int (&at)[2],
                                                f32x4 (&acc0)[SW_MAXT], f32x4 (&acc1)[SW_MAXT]) {
-  if constexpr (StagedRegs<KC, PT>::n <= STAGED_MAX_REGS) {
+  // larger staged shapes spilled and measured slower on the 4096-pair batch
+  if constexpr (StagedRegs<KC, PT>::n <= 160) {
     lds16_tiles_staged<KC, PT, NT>(op, In, lo, stage, na, at, acc0, acc1);
   } else {
     // too many registers for a staged trip: each wave streams its own G_B
