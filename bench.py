@@ -42,7 +42,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--parts", default="pair10,mpo8,batch,layer4")
     ap.add_argument("--no-beside", action="store_true",
-                    help="skip the measurements beside the step (BF16 batch, plain loop, BF16 layer)")
+                    help="skip the measurements beside the step (BF16 batch, plain loop, BF16 layer, measured peaks)")
     ap.add_argument("--batch-dtype", default="f32", choices=["f32", "bf16"],
                     help="core dtype of the batch part (bf16: the BF16 schedule as the timed part, for profiling it)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -173,6 +173,46 @@ def algorithmic(W):
         fwd = gemm + chain
         out["layer4"] = dict(flops=fwd + 2 * gemm + chain + proj, fwd_flops=fwd, gemm_flops=gemm,
                              bytes=4.0 * B * D * 6)
+    return out
+
+
+# ------------------------------------------------------------- measured peaks
+def measured_peaks(W, stream):
+    """Reference rates measured on this GPU beside the nominal peaks: a
+    plain 1 GiB device copy (bytes read + written per second) for HBM, and
+    the vendor FP32 GEMM (torch.mm, hipBLASLt) on the layer's forward shape
+    for FP32 MFMA.  Neither is part of the path; they only give the
+    achieved rates a second scale."""
+    import torch
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    out = {}
+    n = 1 << 28
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    ms = timed(lambda: dst.copy_(src), 10)
+    out["hbm_copy_GBs"] = round(2 * 4 * n / (ms * 1e-3) / 1e9, 1)
+    del src, dst
+    if "layer4" in W:
+        X = W["layer4"]["X"]
+        g = torch.Generator(device="cuda:0")
+        g.manual_seed(1)
+        Wt = torch.randn(4096, 4096, dtype=torch.float32, device="cuda:0", generator=g)
+        ms = timed(lambda: torch.mm(X, Wt), 5)
+        out["fp32_gemm_TFLOPs"] = round(2.0 * X.shape[0] * 4096 * 4096 / (ms * 1e-3) / 1e12, 2)
+        del Wt
+    torch.cuda.synchronize()
     return out
 
 
@@ -377,7 +417,19 @@ def main():
         roof = {"bound": "hbm", "kernel": dominant, "achieved": round(ach, 1), "peak": PEAK["hbm_GBs"],
                 "unit": "GB/s", "frac": round(ach / PEAK["hbm_GBs"], 4), "traffic": None}
 
+    if not args.no_beside:
+        mp = measured_peaks(W, stream)
+        if roof["unit"] == "GB/s" and "hbm_copy_GBs" in mp:
+            roof["measured_peak"] = {"value": mp["hbm_copy_GBs"], "what": "1 GiB device copy, bytes read + written"}
+            roof["frac_of_measured"] = round(roof["achieved"] / mp["hbm_copy_GBs"], 4)
+        elif roof["unit"] == "TFLOP/s" and "fp32_gemm_TFLOPs" in mp:
+            roof["measured_peak"] = {"value": mp["fp32_gemm_TFLOPs"],
+                                     "what": "vendor FP32 GEMM (torch.mm) on the same 8192 x 4096 x 4096 shape"}
+            roof["frac_of_measured"] = round(roof["achieved"] / mp["fp32_gemm_TFLOPs"], 4)
+
     beside = {}
+    if not args.no_beside:
+        beside["measured_peaks"] = mp
     if "batch" in parts and not args.no_beside and args.batch_dtype == "f32":
         d = W["batch"]
         plan = d["plan"]
@@ -399,7 +451,8 @@ def main():
                                 "contractions_per_s": round(8192 / (part_ms["batch"] * 1e-3), 1),
                                 "GBs": parts_out["batch"]["GBs"], "TFLOPs": parts_out["batch"]["TFLOPs"],
                                 "algorithmic_GB": round(plan.bytes / 1e9, 3),
-                                "algorithmic_GFLOP": round(plan.flops / 1e9, 3)}
+                                "algorithmic_GFLOP": round(plan.flops / 1e9, 3),
+                                "frac_of_copy": round(parts_out["batch"]["GBs"] / mp["hbm_copy_GBs"], 4)}
         from ttgen import configs as C
         pairs_bf = C.gen_batch_torch(C.SEED_BATCH, d["shapes"], "cuda", torch.bfloat16)
         plan_bf = ttc.BatchPlan(pairs_bf)
@@ -410,6 +463,7 @@ def main():
                                 "GBs": round(plan_bf.bytes / (bf_ms * 1e-3) / 1e9, 1),
                                 "TFLOPs": round(plan_bf.flops / (bf_ms * 1e-3) / 1e12, 3),
                                 "algorithmic_GB": round(plan_bf.bytes / 1e9, 3),
+                                "frac_of_copy": round(plan_bf.bytes / (bf_ms * 1e-3) / 1e9 / mp["hbm_copy_GBs"], 4),
                                 "schedule": plan_bf.config}
         del pairs_bf, plan_bf, ib, jb
     if "layer4" in parts and not args.no_beside:
