@@ -111,10 +111,13 @@ typedef struct {
  * the first step is the paper's K = A_x^T A_y (Section III, Example 1 and
  * Algorithm 2, step 4).  Right to left, V_N = [1] and
  *   V_{k-1} = sum_i G_x^(k)[:, i, :] V_k G_y^(k)[:, i, :]^T.
- * FP32 and BF16 pairs with every rank <= 128 take one right-to-left sweep
- * whose interface stays in LDS, finished with the first cores in FP64 (no
- * workspace).  Otherwise the two sweeps meet at a middle bond c:
- * z = sum W_c .* V_c, accumulated in FP64.  X and Y need equal order and
+ * FP32 and BF16 pairs with every rank <= 128 keep the interfaces in LDS:
+ * below order 4 one right-to-left sweep finished with the first cores in
+ * FP64 (no workspace); from order 4 two such sweeps at once, V_c over cores
+ * c..N-1 and W_c over the reversed prefix (c = N / 2; workspace: the two
+ * R_c x P_c FP32 interfaces and rank-transposed copies of the prefix cores).
+ * Otherwise the two sweeps meet at c in the chained-MFMA kernels.  Either
+ * way z = sum W_c .* V_c, accumulated in FP64.  X and Y need equal order and
  * mode sizes; their ranks may differ.
  * x, y:   descriptors, same dtype.
  * prec:   AUTO, or the precision AUTO would pick.

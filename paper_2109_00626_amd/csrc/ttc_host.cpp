@@ -317,6 +317,31 @@ ttc_status run_junction(const ttc_tt* x, const ttc_tt* y, BlockKind kind, int k,
 // Bidirectional inner product meeting at bond N/2.
 ttc_status run_inner(const ttc_tt* x, const ttc_tt* y, double* d_out, Arena& ws, size_t ws_bytes, bool sizing,
                      hipStream_t s) {
+  if (lds_path(x, y) && x->order >= 4) {
+    // two half sweeps at once, one workgroup each, meeting at bond c: V_c right
+    // to left over cores c..N-1, W_c as the right-to-left sweep of the
+    // reversed, rank-transposed prefix (cores 0..c-1); then <X, Y> = sum W_c .* V_c
+    const int c = x->order / 2;
+    const size_t rp = (size_t)x->ranks[c] * y->ranks[c];
+    void* W = ws.take(rp * sizeof(float));
+    void* V = ws.take(rp * sizeof(float));
+    PairLdsArgs pa;
+    std::memset(&pa, 0, sizeof(pa));
+    CoreRevArgs ra;
+    reversed_pair(x, y, c, ws, &pa.side[1].x, &pa.side[1].y, &ra);
+    pa.side[1].stop = 0;
+    pa.side[0].x = to_dev(x);
+    pa.side[0].y = to_dev(y);
+    pa.side[0].stop = c;
+    if (sizing) return TTC_OK;
+    if (ws.off > ws_bytes) return fail(TTC_ERR_WORKSPACE, "workspace too small");
+    pa.side[0].out = reinterpret_cast<float*>(V);
+    pa.side[1].out = reinterpret_cast<float*>(W);
+    TTC_HIP(launch_core_reverse(ra, s));
+    TTC_HIP(launch_pair_lds(x->dtype, pa, 2, s));
+    TTC_HIP(launch_meet(x->dtype, W, V, (int)rp, d_out, s));
+    return TTC_OK;
+  }
   if (lds_path(x, y)) {
     // one right-to-left sweep with the interface in LDS, then the first cores
     if (sizing) return TTC_OK;

@@ -69,7 +69,13 @@ def test_inner_validation(lib, abi):
     x = Desc(abi, [3, 4], [1, 2, 1])
     y = Desc(abi, [3, 4], [1, 5, 1])
     assert lib.tt_contract_inner_query(byref(x.s), byref(y.s), 0, byref(need)) == 0
-    assert need.value == 0  # FP32, ranks <= 128: one LDS-resident sweep, no workspace
+    assert need.value == 0  # FP32, ranks <= 128, order < 4: one LDS-resident sweep, no workspace
+    x4 = Desc(abi, [3, 4, 5, 6], [1, 2, 7, 3, 1])
+    y4 = Desc(abi, [3, 4, 5, 6], [1, 5, 9, 2, 1])
+    assert lib.tt_contract_inner_query(byref(x4.s), byref(y4.s), 0, byref(need)) == 0
+    # order 4: two LDS sweeps meeting at bond 2; W_2 and V_2 (7 x 9 FP32 each)
+    # plus the reversed prefix cores (3*2 + 2*4*7 and 3*5 + 5*4*9 FP32)
+    assert need.value >= 4 * (2 * 7 * 9 + 6 + 56 + 15 + 180)
     x64 = Desc(abi, [3, 4], [1, 2, 1], dtype=0)
     y64 = Desc(abi, [3, 4], [1, 5, 1], dtype=0)
     assert lib.tt_contract_inner_query(byref(x64.s), byref(y64.s), 0, byref(need)) == 0
