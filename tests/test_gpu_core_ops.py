@@ -56,13 +56,17 @@ def test_inner_pair10(ttc, dtype):
     ([6, 9], [1, 7, 1], [1, 12, 1]),                                        # order 2
     ([16, 32, 8], [1, 128, 100, 1], [1, 90, 128, 1]),                       # large ranks
     ([2, 3, 2, 3, 2, 3, 2], [1, 2, 3, 4, 5, 4, 3, 1], [1, 1, 2, 1, 2, 1, 2, 1]),
+    ([8, 4, 16, 4, 8, 4], [1, 64, 128, 96, 128, 50, 1], [1, 100, 128, 77, 128, 33, 1]),  # two halves, wide middle bond
 ])
-@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
 def test_inner_ragged(ttc, case, dtype):
     modes, rx, ry = case
     x, y = random_pair(77, modes, rx, ry)
-    e, _ = _inner_case(ttc, x, y, dtype)
-    assert e <= TOL[dtype]
+    e, et = _inner_case(ttc, x, y, dtype)
+    # BF16 cores: the single-pair sweeps compute in FP32, so the error on
+    # the rounded values meets the FP32 bound; the total error the BF16 one
+    assert e <= (TOL["f32"] if dtype == "bf16" else TOL[dtype])
+    assert et <= TOL[dtype]
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
