@@ -7,7 +7,8 @@
 // The carried-bond cores are block-diagonal copies: almost all of their
 // entries are zero, so the kernel is a pure HBM write stream.  Work is split
 // into lines (one fixed row bond and mode index, d1 contiguous outputs);
-// each thread writes 4 consecutive outputs with one 16-byte store.
+// each thread writes 4 consecutive outputs with one 16-byte store, the
+// block-diagonal cores without a division per output.
 //
 // Dense form (small cases): every output entry is the product of the core
 // slices along its multi-index (eq. (9)).
@@ -57,7 +58,25 @@ __global__ __launch_bounds__(256) void lift_kernel(LiftArgs a) {
   const Tc* K = reinterpret_cast<const Tc*>(a.K);
   Tc* dst = reinterpret_cast<Tc*>(c.dst) + (long)l * c.d1;
   const int d1 = c.d1;
-  if (sizeof(Tc) == 4 && (d1 & 3) == 0) {
+  if (sizeof(Tc) == 4 && (d1 & 3) == 0 && c.op == LIFT_DELTA && (a.Q & 3) == 0) {
+    // block-diagonal copy: in line (row, i) only the columns b*Q + q hold
+    // entries (row = a*Q + q); the four columns of a thread share b, so one
+    // division per four outputs and at most one load
+    const int ra = row / a.Q, q = row - ra * a.Q;
+    const Tin* src = reinterpret_cast<const Tin*>(c.src) + ((long)ra * c.n + i) * c.r1;
+    for (int j = 4 * threadIdx.x; j < d1; j += 4 * blockDim.x) {
+      const int b = j / a.Q, u = q - (j - b * a.Q);
+      f32x4 v = {0.f, 0.f, 0.f, 0.f};
+      if (u >= 0 && u < 4) {
+        const float e = (float)cvt<Tc>(src[b]);
+        v[0] = u == 0 ? e : 0.f;
+        v[1] = u == 1 ? e : 0.f;
+        v[2] = u == 2 ? e : 0.f;
+        v[3] = u == 3 ? e : 0.f;
+      }
+      __builtin_nontemporal_store(v, reinterpret_cast<f32x4*>(dst + j));
+    }
+  } else if (sizeof(Tc) == 4 && (d1 & 3) == 0) {
     for (int j = 4 * threadIdx.x; j < d1; j += 4 * blockDim.x) {
       f32x4 v;
       v[0] = (float)lift_value<Tin, Tc>(c, K, a.Q, row, i, j);
