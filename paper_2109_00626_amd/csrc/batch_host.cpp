@@ -301,12 +301,14 @@ hipError_t run_mode(ttc_plan* P, double* inner, float* junc, hipStream_t s) {
 // Largest number of LDS-resident workgroups per CU (bufs: interface buffers
 // per workgroup).
 int lds_kernel_per_cu(const ttc_plan* P, int bufs) {
-  if (bufs == 0) {
-    // BF16-MFMA variant: one interface buffer (two BF16 planes) and the stage when enabled
-    const int bytes = P->buf_elems * (int)sizeof(float) + (P->stage16 ? kBatchStageBytes : 0) + kStaticLds;
-    return std::max(1, std::min(2, (160 * 1024) / bytes));
-  }
   const int bytes = bufs * P->buf_elems * (int)sizeof(float) + 4 * 1024;
+  return std::max(1, std::min(2, (160 * 1024) / bytes));
+}
+
+// The same for the BF16-MFMA variant: one interface buffer (two BF16 planes)
+// and, when enabled, the G_B stage.
+int lds16_kernel_per_cu(const ttc_plan* P) {
+  const int bytes = P->buf_elems * (int)sizeof(float) + (P->stage16 ? kBatchStageBytes : 0) + kStaticLds;
   return std::max(1, std::min(2, (160 * 1024) / bytes));
 }
 
@@ -393,7 +395,7 @@ ttc_status autotune(ttc_plan* P) {
   }
   std::vector<LaunchCfg> cands;
   if (P->dt == TTC_BF16 && (want < 0 || want == 4))
-    for (int pc = 1; pc <= lds_kernel_per_cu(P, 0); ++pc) cands.push_back({4, 256, pc});
+    for (int pc = 1; pc <= lds16_kernel_per_cu(P); ++pc) cands.push_back({4, 256, pc});
   if (want < 0 || want == 3)
     for (int pc = 1; pc <= lds_kernel_per_cu(P, 1); ++pc) cands.push_back({3, 256, pc});
   if (want < 0 || want == 2) {
