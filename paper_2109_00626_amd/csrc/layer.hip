@@ -474,13 +474,12 @@ template <bool A_KC, bool B_KC, bool BF16>
 static hipError_t gemm_launch(const GemmArgs& g, hipStream_t s) {
   constexpr int esz = BF16 ? 2 : 4;
   const size_t lds = (size_t)4 * tile_elems<BF16>() * esz;
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm_kernel<A_KC, B_KC, BF16>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
+  static std::atomic<bool> done[kMaxDevices];
+  const hipError_t e = once_per_device(done, [&] {
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm_kernel<A_KC, B_KC, BF16>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  });
+  if (e != hipSuccess) return e;
   const int tiles = ((g.M + GBM - 1) / GBM) * ((g.N + GBN - 1) / GBN);
   hipLaunchKernelGGL((gemm_kernel<A_KC, B_KC, BF16>), dim3(tiles, g.splits), dim3(256), lds, s, g);
   return hipGetLastError();

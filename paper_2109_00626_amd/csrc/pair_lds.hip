@@ -125,18 +125,18 @@ hipError_t launch_pair_lds(ttc_dtype dt, const PairLdsArgs& a, int nsides, hipSt
   int floats = 0;
   for (int q = 0; q < nsides; ++q) floats = std::max(floats, side_lds_floats(a.side[q]));
   const int bytes = floats * (int)sizeof(float);
-  static bool attr_set = false;
-  if (!attr_set) {
+  static std::atomic<bool> done[kMaxDevices];
+  const hipError_t e = once_per_device(done, [] {
     // the largest buffer any qualifying pair needs (ranks 128)
     const int most = lds_iface_elems(128, 128) * (int)sizeof(float);
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&pair_lds_kernel<float>),
+    hipError_t r = hipFuncSetAttribute(reinterpret_cast<const void*>(&pair_lds_kernel<float>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, most);
-    if (e == hipSuccess)
-      e = hipFuncSetAttribute(reinterpret_cast<const void*>(&pair_lds_kernel<bf16_t>),
+    if (r == hipSuccess)
+      r = hipFuncSetAttribute(reinterpret_cast<const void*>(&pair_lds_kernel<bf16_t>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, most);
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
+    return r;
+  });
+  if (e != hipSuccess) return e;
   if (dt == TTC_BF16) hipLaunchKernelGGL((pair_lds_kernel<bf16_t>), dim3(nsides), dim3(256), bytes, s, a);
   else hipLaunchKernelGGL((pair_lds_kernel<float>), dim3(nsides), dim3(256), bytes, s, a);
   return hipGetLastError();

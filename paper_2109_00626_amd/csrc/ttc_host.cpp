@@ -5,7 +5,6 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
-#include <mutex>
 #include <string>
 #include <vector>
 
@@ -42,9 +41,8 @@ size_t comp_size(ttc_dtype d) { return d == TTC_F64 ? 8 : 4; }
 bool dtype_ok(int d) { return d == TTC_F64 || d == TTC_F32 || d == TTC_BF16; }
 
 ttc_status ensure_init() {
-  static std::once_flag once;
-  static hipError_t st = hipSuccess;
-  std::call_once(once, [] { st = sweep_set_lds_limits(); });
+  static std::atomic<bool> done[kMaxDevices];
+  const hipError_t st = once_per_device(done, [] { return sweep_set_lds_limits(); });
   if (st != hipSuccess) return fail(TTC_ERR_HIP, std::string("kernel attribute setup: ") + hipGetErrorString(st));
   return TTC_OK;
 }

@@ -4,9 +4,28 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
+
 #include "../../include/ttc.h"
 
 namespace ttc {
+
+// Runs set() the first time it is reached with a given device current and
+// again only after a failure: a kernel's dynamic-LDS limit is a setting of
+// each device.  Two threads arriving together may both run set(), which only
+// repeats the same attribute write.
+constexpr int kMaxDevices = 64;
+template <typename F>
+hipError_t once_per_device(std::atomic<bool> (&done)[kMaxDevices], F&& set) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return set();
+  if (done[dev].load(std::memory_order_acquire)) return hipSuccess;
+  e = set();
+  if (e == hipSuccess) done[dev].store(true, std::memory_order_release);
+  return e;
+}
 
 // TT descriptor passed by value to kernels (device core pointers).
 struct TTDev {
