@@ -31,6 +31,11 @@
  *  - `stream` is a hipStream_t passed as void* (0 = the null stream).  Calls
  *    are asynchronous on that stream and never synchronise the host, except
  *    tt_batch_plan_create.
+ *  - Each call runs on the device current on the calling host thread; its
+ *    buffers and stream must belong to that device, and a batched plan
+ *    belongs to the device current when it was created.  Calls may come from
+ *    several host threads at once; two calls that share a workspace or a
+ *    plan must be ordered by the caller (one stream, or an event between).
  *  - Errors: every call validates all arguments on the host before any
  *    launch.  On error it returns a non-zero ttc_status, writes no output
  *    byte, and sets a thread-local message readable with ttc_last_error().
