@@ -90,6 +90,59 @@ def test_inner_deterministic(ttc):
     assert a == b
 
 
+def test_inner_from_host_threads(ttc):
+    """Four host threads, each on its own stream with its own inputs and
+    workspace, call the inner product at the same time (FP64 chained sweeps,
+    FP32 and BF16 two-half LDS sweeps, an FP32 single sweep below order 4).
+    Every result equals the same call made alone, bit for bit, and the FP64
+    oracle within the dtype's tolerance."""
+    import threading
+
+    import torch
+
+    cases = [("f64", [6, 4, 8, 5, 3], [1, 9, 17, 12, 4, 1], [1, 5, 33, 8, 6, 1]),
+             ("f32", [8, 4, 16, 4, 8, 4], [1, 64, 128, 96, 128, 50, 1], [1, 100, 128, 77, 128, 33, 1]),
+             ("bf16", [16, 8, 4, 8, 16], [1, 16, 70, 33, 16, 1], [1, 16, 40, 65, 12, 1]),
+             ("f32", [32, 64, 16], [1, 32, 100, 1], [1, 20, 128, 1])]
+    inputs, alone = [], []
+    for n, (dtype, modes, rx, ry) in enumerate(cases):
+        x, y = random_pair(500 + n, modes, rx, ry)
+        xg, xs = to_gpu(x, dtype)
+        yg, ys = to_gpu(y, dtype)
+        z = float(ttc.tt_contract_inner(xg, yg).item())
+        assert scalar_err(z, O.inner_lr(xs, ys), tt_norm(xs), tt_norm(ys)) <= (TOL["f32"] if dtype == "bf16" else TOL[dtype])
+        inputs.append((xg, yg))
+        alone.append(z)
+    torch.cuda.synchronize()
+    reps = 25
+    got = [None] * len(cases)
+    errors = []
+    start = threading.Barrier(len(cases))
+
+    def work(n):
+        try:
+            s = torch.cuda.Stream()
+            xg, yg = inputs[n]
+            start.wait()
+            with torch.cuda.stream(s):
+                outs = [ttc.tt_contract_inner(xg, yg) for _ in range(reps)]
+            s.synchronize()
+            got[n] = [float(o.item()) for o in outs]
+        except Exception as exc:  # re-raised in the main thread
+            errors.append(exc)
+
+    threads = [threading.Thread(target=work, args=(n,)) for n in range(len(cases))]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join(timeout=120)
+    assert not any(t.is_alive() for t in threads)
+    if errors:
+        raise errors[0]
+    for n in range(len(cases)):
+        assert got[n] == [alone[n]] * reps, (cases[n][0], n)
+
+
 # ------------------------------------------------------------------ modes
 def test_modes_inner4_all_forms(ttc):
     sx, sy = C.inner4_shapes()
