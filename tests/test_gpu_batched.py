@@ -224,3 +224,66 @@ def test_batch_bf16_odd_modes_wide_ranks(ttc, monkeypatch, mode):
     for p, (z, K) in enumerate(want):
         assert float(inner[p]) == z
         assert np.array_equal(to_np(plan.junction(junc, p)), K)
+
+
+def test_batch_plans_from_host_threads(ttc, tmp_path, monkeypatch):
+    """Two host threads each build a plan for a batch of their own (FP32 and
+    BF16 cores) and run it on a stream of their own at the same time,
+    alternating two output buffers so that every run captures a new graph.
+    Each result equals the same batch run alone, bit for bit.  The tuner's
+    cache file, written by the runs alone, gives the threads' plans the same
+    schedule (without it each plan is timed again, under the other thread's
+    load)."""
+    import threading
+
+    import torch
+
+    monkeypatch.setenv("TTC_AUTOTUNE_CACHE", str(tmp_path / "tune.txt"))
+    batches = []
+    for n, dtype in enumerate(("f32", "bf16")):
+        seed = C.SEED_BATCH + 11 + n
+        gpu = []
+        for p, (sx, sy) in enumerate(C.batch_pair_shapes(seed, 24)):
+            xg, _ = to_gpu(C.gen_tt_np(seed, 1 + 2 * p, sx), dtype)
+            yg, _ = to_gpu(C.gen_tt_np(seed, 2 + 2 * p, sy), dtype)
+            gpu.append((xg, yg))
+        plan = ttc.BatchPlan(gpu)
+        inner, junc = plan.run()
+        batches.append((gpu, plan.config, to_np(inner), to_np(junc)))
+    torch.cuda.synchronize()
+    reps = 6
+    got = [None] * len(batches)
+    errors = []
+    start = threading.Barrier(len(batches))
+
+    def work(n):
+        try:
+            gpu = batches[n][0]
+            s = torch.cuda.Stream()
+            start.wait()
+            with torch.cuda.stream(s):
+                plan = ttc.BatchPlan(gpu)
+                bufs = [plan.outputs(), plan.outputs()]
+                outs = []
+                for r in range(reps):
+                    inner, junc = bufs[r % 2]
+                    plan.run(inner, junc)
+                    outs.append((inner.clone(), junc.clone()))
+            s.synchronize()
+            got[n] = (plan.config, [(to_np(i), to_np(j)) for i, j in outs])
+        except Exception as exc:  # re-raised in the main thread
+            errors.append(exc)
+
+    threads = [threading.Thread(target=work, args=(n,)) for n in range(len(batches))]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join(timeout=120)
+    assert not any(t.is_alive() for t in threads)
+    if errors:
+        raise errors[0]
+    for n, (_, config, inner0, junc0) in enumerate(batches):
+        cfg, outs = got[n]
+        assert cfg == config
+        for inner, junc in outs:
+            assert np.array_equal(inner, inner0) and np.array_equal(junc, junc0), n
