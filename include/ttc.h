@@ -227,11 +227,13 @@ ttc_status ttc_mse_loss(const float* d_y, const float* d_t, int64_t n, double* d
  * gradient *d_gz (one device double):
  *   dz/dG_x^(k)[:, i, :] = W_k G_y^(k)[:, i, :] V_{k+1}^T,
  *   dz/dG_y^(k)[:, i, :] = W_k^T G_x^(k)[:, i, :] V_{k+1},
- * with W_k the left interface of core k and V_{k+1} the right one.  FP32 and
- * BF16 pairs with every rank <= 128 store every interface (2 N max_k R_k P_k
- * floats of workspace; ckpt_stride is ignored).  Otherwise only every
- * ckpt_stride-th interface is kept and the rest are recomputed
- * (ckpt_stride <= 0 picks about sqrt(N)).  d_dx[k], d_dy[k]: device buffers shaped like the
+ * with W_k the left interface of core k and V_{k+1} the right one.
+ * ckpt_stride > 0: a forward sweep keeps every ckpt_stride-th interface and
+ * each segment between two kept ones is recomputed (memory for long trains).
+ * ckpt_stride <= 0: FP32 and BF16 pairs with every rank <= 128 store every
+ * interface from two LDS-resident sweeps (2 N max_k R_k P_k floats of
+ * workspace); other pairs keep every ceil(sqrt(N))-th interface.
+ * d_dx[k], d_dy[k]: device buffers shaped like the
  * cores, same dtype class (FP64 for FP64, FP32 otherwise); either list may
  * be NULL to skip that side.
  * ------------------------------------------------------------------------ */
@@ -285,6 +287,12 @@ ttc_status tt_batch_plan_info(const ttc_plan* plan, int64_t* junction_offsets, d
  * lo pair (16 significant bits);
  * threads = workgroup size; wg_per_cu = workgroups per compute unit. */
 ttc_status tt_batch_plan_config(const ttc_plan* plan, int32_t* mode, int32_t* threads, int32_t* wg_per_cu);
+/* One run of the plan: the selected schedule's launch(es), captured once per
+ * (d_inner, d_junction) pair into a HIP graph on the plan's own stream and
+ * replayed on `stream` (any stream, the null stream included).  The plan
+ * keeps the graphs of the last four output-pointer pairs; an older one is
+ * destroyed only after its last replay has finished (an event recorded
+ * after every replay). */
 ttc_status tt_batch_run(ttc_plan* plan, double* d_inner, float* d_junction, void* stream);
 /* The same pairs as one single-pair launch sequence each (the plain loop
  * that the batched launch replaces); same outputs. */

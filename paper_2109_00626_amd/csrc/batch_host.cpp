@@ -93,12 +93,20 @@ struct ttc_plan {
   long* d_vcap = nullptr;
   float* d_one = nullptr;
   size_t lvl_lds = 0, meet_lds = 0;
-  // graph
+  // graphs: one captured launch per output-pointer pair, at most kGraphs
+  // kept; `done` is recorded after every replay, so an entry is destroyed
+  // only once its last replay has finished
+  struct GraphEntry {
+    double* inner = nullptr;
+    float* junc = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t done = nullptr;
+    uint64_t used = 0;
+  };
   hipStream_t cap_stream = nullptr;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  double* g_inner = nullptr;
-  float* g_junc = nullptr;
+  std::vector<GraphEntry> graphs;
+  uint64_t use_clock = 0;
 };
 
 namespace {
@@ -445,15 +453,64 @@ ttc_status autotune(ttc_plan* P) {
   return upload_assignment(P, best, &P->grid, &P->lds_elems);
 }
 
+void destroy_graph(ttc_plan::GraphEntry& g) {
+  if (g.done) (void)hipEventSynchronize(g.done);
+  if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  if (g.graph) (void)hipGraphDestroy(g.graph);
+  if (g.done) (void)hipEventDestroy(g.done);
+  g = ttc_plan::GraphEntry();
+}
+
+const size_t kGraphs = 4;
+
+// The graph entry that replays the plan's launch into (d_inner,
+// d_junction): found, or captured on the plan's own stream (thread-local
+// capture, so other threads' work is not captured), evicting the least
+// recently used entry after its last replay has finished.
+ttc_status graph_for(ttc_plan* P, double* d_inner, float* d_junction, ttc_plan::GraphEntry** out) {
+  for (auto& g : P->graphs)
+    if (g.inner == d_inner && g.junc == d_junction) {
+      g.used = ++P->use_clock;
+      *out = &g;
+      return TTC_OK;
+    }
+  if (P->graphs.size() >= kGraphs) {
+    size_t lru = 0;
+    for (size_t i = 1; i < P->graphs.size(); ++i)
+      if (P->graphs[i].used < P->graphs[lru].used) lru = i;
+    destroy_graph(P->graphs[lru]);
+    P->graphs.erase(P->graphs.begin() + lru);
+  }
+  if (!P->cap_stream) TTC_HIP(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking));
+  ttc_plan::GraphEntry g;
+  TTC_HIP(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal));
+  hipError_t le = run_mode(P, d_inner, d_junction, P->cap_stream);
+  hipError_t ce = hipStreamEndCapture(P->cap_stream, &g.graph);
+  if (le != hipSuccess || ce != hipSuccess) {
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+    return fail(TTC_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(le != hipSuccess ? le : ce));
+  }
+  hipError_t ie = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
+  if (ie == hipSuccess) ie = hipEventCreateWithFlags(&g.done, hipEventDisableTiming);
+  if (ie != hipSuccess) {
+    destroy_graph(g);
+    return fail(TTC_ERR_HIP, std::string("graph instantiate: ") + hipGetErrorString(ie));
+  }
+  g.inner = d_inner;
+  g.junc = d_junction;
+  g.used = ++P->use_clock;
+  P->graphs.push_back(g);
+  *out = &P->graphs.back();
+  return TTC_OK;
+}
+
 void release(ttc_plan* P) {
-  if (P->exec) (void)hipGraphExecDestroy(P->exec);
-  if (P->graph) (void)hipGraphDestroy(P->graph);
+  for (auto& g : P->graphs) destroy_graph(g);
+  P->graphs.clear();
   if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
   if (P->dmem) (void)hipFree(P->dmem);
   if (P->dmem_levels) (void)hipFree(P->dmem_levels);
   P->dmem_levels = nullptr;
-  P->exec = nullptr;
-  P->graph = nullptr;
   P->cap_stream = nullptr;
   P->dmem = nullptr;
 }
@@ -696,32 +753,10 @@ ttc_status tt_batch_run(ttc_plan* P, double* d_inner, float* d_junction, void* s
   if ((P->ops & TTC_OP_INNER) && !d_inner) return fail(TTC_ERR_NULL, "d_inner is NULL");
   if ((P->ops & TTC_OP_SUFFIX2) && !d_junction) return fail(TTC_ERR_NULL, "d_junction is NULL");
   hipStream_t s = (hipStream_t)stream;
-  if (!s) {
-    TTC_HIP(run_mode(P, d_inner, d_junction, s));
-    return TTC_OK;
-  }
-  if (!P->exec || P->g_inner != d_inner || P->g_junc != d_junction) {
-    if (P->exec) {
-      (void)hipGraphExecDestroy(P->exec);
-      P->exec = nullptr;
-    }
-    if (P->graph) {
-      (void)hipGraphDestroy(P->graph);
-      P->graph = nullptr;
-    }
-    if (!P->cap_stream) TTC_HIP(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking));
-    TTC_HIP(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal));
-    hipError_t le = run_mode(P, d_inner, d_junction, P->cap_stream);
-    hipGraph_t g = nullptr;
-    hipError_t ce = hipStreamEndCapture(P->cap_stream, &g);
-    if (le != hipSuccess) return fail(TTC_ERR_HIP, std::string("capture launch: ") + hipGetErrorString(le));
-    if (ce != hipSuccess) return fail(TTC_ERR_HIP, std::string("end capture: ") + hipGetErrorString(ce));
-    P->graph = g;
-    TTC_HIP(hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0));
-    P->g_inner = d_inner;
-    P->g_junc = d_junction;
-  }
-  TTC_HIP(hipGraphLaunch(P->exec, s));
+  ttc_plan::GraphEntry* g = nullptr;
+  TTC_TRY(graph_for(P, d_inner, d_junction, &g));
+  TTC_HIP(hipGraphLaunch(g->exec, s));
+  TTC_HIP(hipEventRecord(g->done, s));
   return TTC_OK;
 }
 

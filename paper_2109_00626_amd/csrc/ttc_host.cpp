@@ -756,6 +756,12 @@ void grad_lds_take(const ttc_tt* x, const ttc_tt* y, Arena& a, GradLds* g) {
   g->gc = grad_core_shape(x, y, sizeof(float));
   g->g_global = g->gc.global ? a.take((size_t)g->gc.blocks * g->gc.elems * sizeof(float)) : nullptr;
 }
+// The gradient stores every interface (LDS-resident sweeps) when the pair
+// takes the LDS path and the caller asked for no checkpoint stride; a
+// positive stride always selects checkpointing with recomputation.
+bool grad_stores_all(const ttc_tt* x, const ttc_tt* y, int32_t ckpt_stride) {
+  return ckpt_stride <= 0 && lds_path(x, y);
+}
 }  // namespace
 
 extern "C" {
@@ -763,7 +769,7 @@ extern "C" {
 ttc_status tt_contract_inner_bwd_query(const ttc_tt* x, const ttc_tt* y, int32_t ckpt_stride, size_t* ws_bytes) {
   TTC_TRY(check_pair(x, y));
   if (!ws_bytes) return fail(TTC_ERR_NULL, "ws_bytes is NULL");
-  if (lds_path(x, y)) {
+  if (grad_stores_all(x, y, ckpt_stride)) {
     Arena a(nullptr);
     GradLds g;
     grad_lds_take(x, y, a, &g);
@@ -804,7 +810,7 @@ ttc_status tt_contract_inner_bwd(const ttc_tt* x, const ttc_tt* y, const double*
   }
   TTC_TRY(ensure_init());
   hipStream_t s = (hipStream_t)stream;
-  if (lds_path(x, y)) {
+  if (grad_stores_all(x, y, ckpt_stride)) {
     // two workgroups store every interface (V right to left, W as the
     // reversed pair's V), then one wide launch forms every slice
     Arena a(d_ws);

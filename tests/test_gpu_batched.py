@@ -1,8 +1,8 @@
 """GPU parity of the batched sweeps (inner product + junction of
 the contraction over the last two positions, per pair) against the FP64
-oracle, through the C ABI: a small uneven batch checked in full, and the
-4096-pair batch checked on sampled pairs (FP32 and BF16 inputs), against the
-per-pair launch loop, and for run-to-run determinism."""
+oracle, through the C ABI: a small uneven batch and the whole 4096-pair
+batch, every pair checked (FP32 and BF16 inputs, every schedule), the
+per-pair launch loop, and run-to-run determinism."""
 import math
 
 import numpy as np
@@ -11,7 +11,7 @@ import pytest
 from oracle import tt_oracle as O
 from ttgen import configs as C
 
-from helpers import TOL, rel_fro, scalar_err, to_gpu, to_np, tt_norm
+from helpers import TOL, rel_err, scalar_err, to_gpu, to_np, tt_norm
 
 pytestmark = pytest.mark.gpu
 
@@ -29,7 +29,7 @@ def _check_pairs(plan, inner, junc, cores64, idx, tol):
         x, y = cores64[p]
         z, K = _oracle_pair(x, y)
         e = scalar_err(float(inner[p]), z, tt_norm(x), tt_norm(y))
-        ek = rel_fro(to_np(plan.junction(junc, p)), K)
+        ek = rel_err(to_np(plan.junction(junc, p)), K)
         worst = max(worst, e, ek)
         assert e <= tol, (p, e)
         assert ek <= tol, (p, ek)
@@ -110,35 +110,105 @@ def test_batch_integer_cores_exact(ttc, batch_mode):
         assert np.array_equal(to_np(plan.junction(junc, p)), K)
 
 
-@pytest.mark.parametrize("dtype", ["f32", "bf16"])
-def test_batch4096_sampled(ttc, dtype, batch_mode):
-    _skip_f32_only_bf16(batch_mode, dtype)
+_B4096 = {}
+
+
+def _batch4096(dtype):
+    """The 4096-pair batch on the GPU and the oracle's results for every
+    pair, cached per dtype: {"held": ...} from the values the GPU holds
+    (arithmetic error), and for BF16 also {"unrounded": ...} from the FP64
+    values before rounding (total error).  Each entry is (z, K, nx, ny): the
+    inner products, junctions V_{N-2} and the two Frobenius norms, all from
+    the oracle's right-to-left sweep (V_0 is <X, Y>)."""
+    if dtype in _B4096:
+        return _B4096[dtype]
     import torch
     shapes = C.batch_pair_shapes(C.SEED_BATCH, 4096)
     td = torch.float32 if dtype == "f32" else torch.bfloat16
     pairs = C.gen_batch_torch(C.SEED_BATCH, shapes, "cuda", td)
+    refs = {}
+    for name in (("held", "unrounded") if dtype == "bf16" else ("held",)):
+        src = pairs if name == "held" else C.gen_batch_torch(C.SEED_BATCH, shapes, "cuda", torch.float64)
+        n = len(shapes)
+        z, nx, ny, K = np.zeros(n), np.zeros(n), np.zeros(n), []
+        for p in range(n):
+            x = [to_np(t) for t in src[p][0]]
+            y = [to_np(t) for t in src[p][1]]
+            V = O.sweep_rl(x, y)
+            z[p] = V[0][0, 0]
+            K.append(V[len(x) - 2])
+            nx[p], ny[p] = tt_norm(x), tt_norm(y)
+        refs[name] = (z, K, nx, ny)
+        del src
+    torch.cuda.empty_cache()
+    _B4096[dtype] = (shapes, pairs, refs)
+    return _B4096[dtype]
+
+
+def _check_all(plan, inner, junc, ref, tol):
+    """Every pair's inner product (Cauchy-Schwarz scale) and junction
+    (rel_err) against the oracle; returns the worst of each."""
+    z, K, nx, ny = ref
+    e = np.abs(inner - z) / np.maximum(nx * ny, 1e-300)
+    bad = np.flatnonzero(e > tol)
+    assert bad.size == 0, (bad[:10], e[bad[:10]])
+    ek = np.array([rel_err(to_np(plan.junction(junc, p)), K[p]) for p in range(len(K))])
+    bad = np.flatnonzero(ek > tol)
+    assert bad.size == 0, (bad[:10], ek[bad[:10]])
+    return float(e.max()), float(ek.max())
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_batch4096_all_pairs(ttc, dtype, batch_mode):
+    """The 4096-pair batch, every pair's inner product and junction against
+    the oracle (FP32: on the values the GPU holds; BF16: the total error
+    against the unrounded FP64 values and the arithmetic error against the
+    rounded ones), then run-to-run determinism bit for bit."""
+    _skip_f32_only_bf16(batch_mode, dtype)
+    import torch
+    shapes, pairs, refs = _batch4096(dtype)
     plan = ttc.BatchPlan(pairs)
+    assert plan.config["mode"] == batch_mode
     inner, junc = plan.run()
-    inner_np = to_np(inner)
-    rs = np.random.RandomState(1 if dtype == "f32" else 2)
-    # the heaviest pairs and a random sample
-    cost = [sum(sx.ranks[k] * sx.modes[k] * sx.ranks[k + 1] * (sy.ranks[k] + sy.ranks[k + 1])
-                for k in range(sx.order)) for sx, sy in shapes]
-    idx = list(np.argsort(cost)[-3:]) + list(rs.choice(4096, 12, replace=False))
-    cores64 = {}
-    for p in idx:
-        x, y = pairs[p]
-        if dtype == "f32":
-            cores64[p] = ([to_np(t) for t in x], [to_np(t) for t in y])
-        else:  # total error against the unrounded FP64 values
-            cores64[p] = (C.gen_tt_np(C.SEED_BATCH, 1 + 2 * p, shapes[p][0]),
-                          C.gen_tt_np(C.SEED_BATCH, 2 + 2 * p, shapes[p][1]))
-    _check_pairs(plan, inner_np, junc, cores64, idx, TOL[dtype])
-    assert np.all(np.isfinite(inner_np))
+    inner_np, junc_h = to_np(inner), junc.cpu()
+    if dtype == "f32":
+        worst = _check_all(plan, inner_np, junc_h, refs["held"], TOL["f32"])
+    else:
+        worst = _check_all(plan, inner_np, junc_h, refs["unrounded"], TOL["bf16"])
+        worst += _check_all(plan, inner_np, junc_h, refs["held"], ARITH_BF16.get(batch_mode, ARITH_BF16_DEFAULT))
+    print(f"batch4096 {dtype} {batch_mode}: worst errors {worst}")
     inner2, junc2 = plan.outputs()
     plan.run(inner2, junc2)
     assert np.array_equal(to_np(inner2), inner_np)
     assert torch.equal(junc2, junc)
+
+
+def test_batch_graph_replays_many_outputs(ttc):
+    """Runs into six output-buffer pairs, twice round, queued on the null
+    stream with no host synchronisation in between: each new pair captures a
+    graph and, past four, evicts the least recently used one while earlier
+    replays may still be queued.  Every run equals the first bit for bit."""
+    import torch
+    shapes = C.batch_pair_shapes(C.SEED_BATCH + 3, 24)
+    gpu = []
+    for p, (sx, sy) in enumerate(shapes):
+        xg, _ = to_gpu(C.gen_tt_np(C.SEED_BATCH + 3, 1 + 2 * p, sx), "f32")
+        yg, _ = to_gpu(C.gen_tt_np(C.SEED_BATCH + 3, 2 + 2 * p, sy), "f32")
+        gpu.append((xg, yg))
+    plan = ttc.BatchPlan(gpu)
+    inner0, junc0 = plan.run()
+    bufs = [plan.outputs() for _ in range(6)]
+    for b in bufs:
+        b[0].fill_(float("nan"))
+        b[1].fill_(float("nan"))
+    outs = []
+    for r in range(2):
+        for inner, junc in bufs:
+            plan.run(inner, junc)
+            outs.append((inner.clone(), junc.clone()))
+    torch.cuda.synchronize()
+    for inner, junc in outs:
+        assert torch.equal(inner, inner0) and torch.equal(junc, junc0)
 
 
 def test_batch_traced_run(ttc):

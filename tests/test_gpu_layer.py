@@ -6,7 +6,7 @@ import pytest
 from oracle import tt_oracle as O
 from ttgen import configs as C
 
-from helpers import TOL, max_core_rel, rel_fro, to_gpu, to_np
+from helpers import TOL, max_core_rel, rel_err, to_gpu, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -36,12 +36,12 @@ def test_layer_fd_instance(ttc, prec, sched):
     ref = O.layer_forward_backward(ws, Xs, Ts) if prec == "f32" else O.layer_forward_backward(w, X, T)
     tol = TOL[prec]
     Y = ttc.ttm_apply_dense(wg, Xg, prec=prec, sched=sched)
-    assert rel_fro(to_np(Y), ref["Y"]) <= tol
+    assert rel_err(to_np(Y), ref["Y"]) <= tol
     L, dY = ttc.ttc_mse_loss(Y, Tg)
     assert abs(L.item() - ref["L"]) <= tol * ref["L"]
-    assert rel_fro(to_np(dY), ref["dY"]) <= tol
+    assert rel_err(to_np(dY), ref["dY"]) <= tol
     dX, dG = ttc.ttm_apply_dense_bwd(wg, Xg, dY, prec=prec, sched=sched)
-    assert rel_fro(to_np(dX), ref["dX"]) <= tol
+    assert rel_err(to_np(dX), ref["dX"]) <= tol
     assert max_core_rel([to_np(g) for g in dG], ref["dG"]) <= tol
 
 
@@ -59,48 +59,60 @@ def test_layer_autograd_matches_oracle(ttc):
     Y = ttc.tt_linear(xv, cores)
     L, dY = ttc.ttc_mse_loss(Y.detach(), Tg)
     Y.backward(dY)
-    assert rel_fro(to_np(xv.grad), ref["dX"]) <= TOL["f32"]
+    assert rel_err(to_np(xv.grad), ref["dX"]) <= TOL["f32"]
     assert max_core_rel([to_np(c.grad) for c in cores], ref["dG"]) <= TOL["f32"]
 
 
-def test_layer4_full_size(ttc):
-    """Order-4 TT-matrix 4096 -> 4096 (modes 8, ranks 32), batch 8192 x 4096:
-    forward rows and backward rows sampled against the oracle; the loss
-    against its definition on the GPU's Y; the core gradients by the Euler
-    identity <dL/dG_k, G_k> = <dL/dY, Y> (Y is linear in each core), and at a
-    reduced batch of 256 rows against the oracle in full."""
+_L4 = {}
+
+
+def _layer4(ttc):
+    """Full-size layer inputs (order-4 TT-matrix 4096 -> 4096, modes 8, ranks
+    32; X and T 8192 x 4096) and the oracle's FP64 dense route on them,
+    cached: "f32" on the FP32 values the GPU holds, "bf16" on the unrounded
+    FP64 cores (the BF16 option's total error)."""
+    if _L4:
+        return _L4
     import torch
     s = C.layer4_shape()
     w = C.gen_tt_np(C.SEED_LAYER, 1, s)
     wg, ws = to_gpu(w, "f32")
-    B, D = 8192, 4096
-    Xg = C.gen_matrix_torch(C.SEED_LAYER, 2, B, D, "cuda", torch.float32)
-    Tg = C.gen_matrix_torch(C.SEED_LAYER, 3, B, D, "cuda", torch.float32)
-    Y = ttc.ttm_apply_dense(wg, Xg)
-    Wd = O.mpo_full(ws)
-    rows = np.random.RandomState(0).choice(B, 48, replace=False)
-    Xr = to_np(Xg[rows])
-    assert rel_fro(to_np(Y[rows]), Xr @ Wd.T) <= TOL["f32"]
-    L, dY = ttc.ttc_mse_loss(Y, Tg)
+    Xg = C.gen_matrix_torch(C.SEED_LAYER, 2, 8192, 4096, "cuda", torch.float32)
+    Tg = C.gen_matrix_torch(C.SEED_LAYER, 3, 8192, 4096, "cuda", torch.float32)
+    Xn, Tn = to_np(Xg), to_np(Tg)
+    _L4.update(w=w, ws=ws, wg=wg, Xg=Xg, Tg=Tg,
+               f32=O.layer_forward_backward(ws, Xn, Tn),
+               bf16=O.layer_forward_backward(w, Xn, Tn))
+    return _L4
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+@pytest.mark.parametrize("sched", ["dense", "cores"])
+def test_layer4_full_size(ttc, sched, prec):
+    """The full 8192 x 4096 batch through both schedules, FP32 and the BF16
+    MFMA option: Y, the loss, dY, dX and every core gradient against the
+    oracle's dense route, whole arrays (rel_err: relative Frobenius and per
+    row); and the Euler identity <dL/dG_k, G_k> = <dL/dY, Y> for every core
+    (Y is linear in each core)."""
+    d = _layer4(ttc)
+    ref, tol = d[prec], TOL[prec]
+    Y = ttc.ttm_apply_dense(d["wg"], d["Xg"], prec=prec, sched=sched)
     Yn = to_np(Y)
-    Tn = to_np(Tg)
-    Lref = float(np.mean((Yn - Tn) ** 2))
-    assert abs(L.item() - Lref) <= 1e-10 * Lref
-    dX, dG = ttc.ttm_apply_dense_bwd(wg, Xg, dY)
-    dYr = to_np(dY[rows])
-    assert rel_fro(to_np(dX[rows]), dYr @ Wd) <= TOL["f32"]
-    euler = float(np.sum(to_np(dY) * Yn))
+    assert rel_err(Yn, ref["Y"]) <= tol
+    L, dY = ttc.ttc_mse_loss(Y, d["Tg"])
+    assert abs(L.item() - ref["L"]) <= tol * ref["L"]
+    dYn = to_np(dY)
+    assert rel_err(dYn, ref["dY"]) <= tol
+    dX, dG = ttc.ttm_apply_dense_bwd(d["wg"], d["Xg"], dY, prec=prec, sched=sched)
+    assert rel_err(to_np(dX), ref["dX"]) <= tol
+    dGn = [to_np(g) for g in dG]
+    errs = [rel_err(g, r) for g, r in zip(dGn, ref["dG"])]
+    print(f"layer4 {sched} {prec}: dG errors {errs}")
+    assert max(errs) <= tol
+    euler = float(np.sum(dYn * Yn))
     for k in range(4):
-        got = float(np.sum(to_np(dG[k]) * ws[k]))
-        assert abs(got - euler) <= 1e-4 * abs(euler)
-    # reduced batch, full oracle
-    Xs, Ts = Xg[:256].contiguous(), Tg[:256].contiguous()
-    Ys = ttc.ttm_apply_dense(wg, Xs)
-    _, dYs = ttc.ttc_mse_loss(Ys, Ts)
-    dXs, dGs = ttc.ttm_apply_dense_bwd(wg, Xs, dYs)
-    ref = O.layer_forward_backward(ws, to_np(Xs), to_np(Ts))
-    assert rel_fro(to_np(dXs), ref["dX"]) <= TOL["f32"]
-    assert max_core_rel([to_np(g) for g in dGs], ref["dG"]) <= TOL["f32"]
+        got = float(np.sum(dGn[k] * d["ws"][k]))
+        assert abs(got - euler) <= (1e-4 if prec == "f32" else 2e-2) * abs(euler)
 
 
 @pytest.mark.parametrize("sched", ["cores", "dense"])
@@ -123,45 +135,11 @@ def test_layer_cores_schedule(ttc, dims, sched):
     Xg, Tg = _upload(X), _upload(T)
     ref = O.layer_forward_backward(ws, to_np(Xg), to_np(Tg))
     Y = ttc.ttm_apply_dense(wg, Xg, sched=sched)
-    assert rel_fro(to_np(Y), ref["Y"]) <= TOL["f32"]
+    assert rel_err(to_np(Y), ref["Y"]) <= TOL["f32"]
     _, dY = ttc.ttc_mse_loss(Y, Tg)
     dX, dG = ttc.ttm_apply_dense_bwd(wg, Xg, dY, sched=sched)
-    assert rel_fro(to_np(dX), ref["dX"]) <= TOL["f32"]
+    assert rel_err(to_np(dX), ref["dX"]) <= TOL["f32"]
     assert max_core_rel([to_np(g) for g in dG], ref["dG"]) <= TOL["f32"]
-
-
-def test_layer4_cores_full_size(ttc):
-    """The core-by-core schedule at the full 8192 x 4096 batch: forward and
-    dX against the dense schedule's results entrywise and against the oracle
-    on sampled rows; core gradients against the dense schedule's."""
-    import torch
-    s = C.layer4_shape()
-    w = C.gen_tt_np(C.SEED_LAYER, 1, s)
-    wg, ws = to_gpu(w, "f32")
-    Xg = C.gen_matrix_torch(C.SEED_LAYER, 2, 8192, 4096, "cuda", torch.float32)
-    Tg = C.gen_matrix_torch(C.SEED_LAYER, 3, 8192, 4096, "cuda", torch.float32)
-    Yc = ttc.ttm_apply_dense(wg, Xg, sched="cores")
-    Yd = ttc.ttm_apply_dense(wg, Xg, sched="dense")
-    assert float(torch.linalg.vector_norm(Yc - Yd) / torch.linalg.vector_norm(Yd)) <= TOL["f32"]
-    rows = np.random.RandomState(5).choice(8192, 32, replace=False)
-    assert rel_fro(to_np(Yc[rows]), to_np(Xg[rows]) @ O.mpo_full(ws).T) <= TOL["f32"]
-    _, dY = ttc.ttc_mse_loss(Yd, Tg)
-    dXc, dGc = ttc.ttm_apply_dense_bwd(wg, Xg, dY, sched="cores")
-    dXd, dGd = ttc.ttm_apply_dense_bwd(wg, Xg, dY, sched="dense")
-    assert float(torch.linalg.vector_norm(dXc - dXd) / torch.linalg.vector_norm(dXd)) <= TOL["f32"]
-    for a, b in zip(dGc, dGd):
-        assert float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b)) <= TOL["f32"]
-
-
-def test_layer4_bf16_forward(ttc):
-    import torch
-    s = C.layer4_shape()
-    w = C.gen_tt_np(C.SEED_LAYER, 1, s)
-    wg, ws = to_gpu(w, "f32")
-    Xg = C.gen_matrix_torch(C.SEED_LAYER, 2, 512, 4096, "cuda", torch.float32)
-    Y = ttc.ttm_apply_dense(wg, Xg, prec="bf16")
-    ref = to_np(Xg) @ O.mpo_full(w).T
-    assert rel_fro(to_np(Y), ref) <= TOL["bf16"]
 
 
 def test_mse_loss_odd_size(ttc):
@@ -171,4 +149,4 @@ def test_mse_loss_odd_size(ttc):
     L, dy = ttc.ttc_mse_loss(y, t)
     yn, tn = to_np(y), to_np(t)
     assert abs(L.item() - np.mean((yn - tn) ** 2)) <= 1e-12 * np.mean((yn - tn) ** 2)
-    assert rel_fro(to_np(dy), 2 * (yn - tn) / 1001) <= 1e-6
+    assert rel_err(to_np(dy), 2 * (yn - tn) / 1001) <= 1e-6
