@@ -136,6 +136,23 @@ ttc_status tt_contract_inner(const ttc_tt* x, const ttc_tt* y, ttc_prec prec, do
                              void* d_ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
+ * tt_contract_inner without allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  Same arguments, kernels and result as
+ * tt_contract_inner, but the workspace is a fixed array of
+ * TTC_NOALLOC_SCRATCH_BYTES inside the library, one per GPU, held until the
+ * process ends; the call itself allocates nothing.  A pair whose
+ * tt_contract_inner_query size exceeds that returns TTC_ERR_WORKSPACE and
+ * writes nothing.  Every call on one GPU shares that GPU's array: calls that
+ * overlap in time on one GPU (different streams or host threads without an
+ * ordering between them) race and may return wrong results.  No part of the
+ * array needs to start at zero: each call writes every byte it reads.
+ * ------------------------------------------------------------------------ */
+#define TTC_NOALLOC_SCRATCH_BYTES (16u << 20)
+ttc_status tt_contract_inner_noalloc(const ttc_tt* x, const ttc_tt* y, ttc_prec prec, double* d_out,
+                                     void* stream);
+
+/* ------------------------------------------------------------------------
  * Contraction of X and Y over a set of shared positions, each pair summed
  * as in eq. (8) (Def. 6).  The GPU path accepts a prefix {0..k-1}, a suffix
  * {k..N-1} or all positions, at equal positions and sizes in X and Y.

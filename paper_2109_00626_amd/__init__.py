@@ -8,6 +8,7 @@ from .api import (  # noqa: F401
     TTCError,
     tt_contract_inner,
     tt_contract_inner_bwd,
+    tt_contract_inner_noalloc,
     tt_contract_modes,
     tt_contract_modes_query,
     tt_mode_n_product,

@@ -51,6 +51,7 @@ def _declare(lib):
         "ttc_abi_version": (c_int32, []),
         "tt_contract_inner_query": (c_int32, [P(TT), P(TT), c_int32, P(c_size_t)]),
         "tt_contract_inner": (c_int32, [P(TT), P(TT), c_int32, c_void_p, c_void_p, c_size_t, c_void_p]),
+        "tt_contract_inner_noalloc": (c_int32, [P(TT), P(TT), c_int32, c_void_p, c_void_p]),
         "tt_contract_modes_query": (c_int32, [P(TT), P(TT), P(c_int32), c_int32, c_int32, P(c_int32),
                                               P(c_int32), P(c_int32), P(c_int64), P(c_size_t)]),
         "tt_contract_modes": (c_int32, [P(TT), P(TT), P(c_int32), c_int32, c_int32, c_void_p, P(TT),
@@ -98,7 +99,7 @@ def load(path: str = None):
 
 EXPORTED = [
     "ttc_last_error", "ttc_version", "ttc_abi_version",
-    "tt_contract_inner_query", "tt_contract_inner",
+    "tt_contract_inner_query", "tt_contract_inner", "tt_contract_inner_noalloc",
     "tt_contract_modes_query", "tt_contract_modes",
     "tt_mode_n_product",
     "ttm_apply_query", "ttm_apply",

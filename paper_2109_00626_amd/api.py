@@ -112,6 +112,16 @@ def tt_contract_inner(x, y, prec: str = "auto") -> torch.Tensor:
     return out
 
 
+def tt_contract_inner_noalloc(x, y, out: torch.Tensor, prec: str = "auto") -> torch.Tensor:
+    """<X, Y> into `out` (a 0-dim float64 tensor on the cores' device) with
+    the library's fixed workspace: nothing is allocated by this call."""
+    dx, dy = TTDesc(x, "x"), TTDesc(y, "y")
+    if out.dtype != torch.float64 or out.numel() != 1 or out.device != dx.device:
+        raise ValueError("out must be one float64 element on the cores' device")
+    _check(_lib.tt_contract_inner_noalloc(dx.ref, dy.ref, _abi.PREC[prec], _ptr(out), _stream(dx.device)))
+    return out
+
+
 def tt_contract_modes_query(x, y, modes, form: str = "junction"):
     dx, dy = TTDesc(x, "x"), TTDesc(y, "y")
     m = _i32(modes)
