@@ -261,6 +261,33 @@ ttc_status tt_contract_inner_bwd(const ttc_tt* x, const ttc_tt* y, const double*
                                  void* d_ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
+ * TT-SVD (Algorithm 1): the cores of a dense tensor X (row-major over
+ * (i_1, ..., i_N), i_N fastest; FP64 or FP32, computed in that precision with
+ * FP64 dot products).  delta = eps / sqrt(N-1) * ||X||_F; for k = 1..N-1 the
+ * running unfolding (R_{k-1} I_k rows, row index r * I_k + i) is split by an
+ * SVD, the kept rank R_k is the smallest whose discarded singular values have
+ * norm <= delta (at most max_rank when max_rank > 0), core k is the first R_k
+ * left singular vectors and the next running matrix S V^T of those.  eps = 0
+ * keeps every nonzero singular value (the exact TT).
+ *
+ * tt_svd_query: rank_cap (host, N+1; may be NULL) gets the largest rank each
+ *   bond can take; core k needs rank_cap[k] * dims[k] * rank_cap[k+1]
+ *   elements.  ws_bytes: device workspace (three copies of X plus the SVD's
+ *   p x p rotation matrix, p the smaller side of the widest unfolding, at
+ *   most 4096: larger unfoldings return TTC_ERR_UNSUPPORTED).
+ * tt_svd: ranks (host, N+1) receives the ranks; core k is written row-major
+ *   (R_k, I_k, R_{k+1}) at the start of d_cores[k] (device, caller-owned,
+ *   sized from rank_cap).  The ranks depend on the singular values, so the
+ *   call synchronises `stream` once per split (N-1 times) and returns with
+ *   the last copy queued.  X is not modified.
+ * ------------------------------------------------------------------------ */
+ttc_status tt_svd_query(int32_t order, const int32_t* dims, ttc_dtype dtype, int32_t max_rank,
+                        int32_t* rank_cap, size_t* ws_bytes);
+ttc_status tt_svd(const void* d_x, int32_t order, const int32_t* dims, ttc_dtype dtype, double eps,
+                  int32_t max_rank, int32_t* ranks, void* const* d_cores, void* d_ws, size_t ws_bytes,
+                  void* stream);
+
+/* ------------------------------------------------------------------------
  * Batched execution: many independent pairs of uneven order, mode sizes and
  * ranks in one persistent launch, replayed from a HIP graph.  For each pair
  * p the right-to-left sweep gives both results:

@@ -12,6 +12,8 @@ from .api import (  # noqa: F401
     tt_contract_modes,
     tt_contract_modes_query,
     tt_mode_n_product,
+    tt_svd,
+    tt_svd_query,
     ttc_mse_loss,
     ttm_apply,
     ttm_apply_dense,

@@ -122,6 +122,33 @@ def tt_contract_inner_noalloc(x, y, out: torch.Tensor, prec: str = "auto") -> to
     return out
 
 
+def tt_svd_query(dims, dtype=torch.float64, max_rank: int = 0):
+    """(rank capacity per bond, workspace bytes) of tt_svd for a dense tensor
+    of shape `dims`."""
+    n = len(dims)
+    cap = (c_int32 * (n + 1))()
+    need = c_size_t(0)
+    _check(_lib.tt_svd_query(n, _i32(dims), _DT[dtype], int(max_rank), cap, byref(need)))
+    return list(cap), need.value
+
+
+def tt_svd(x: torch.Tensor, eps: float = 0.0, max_rank: int = 0):
+    """TT-SVD (Algorithm 1) of the dense tensor x (FP64 or FP32, on a GPU):
+    list of cores (R_k, I_k, R_{k+1}) on x's device."""
+    if x.device.type != "cuda" or not x.is_contiguous():
+        raise ValueError("x must be a contiguous GPU tensor")
+    dims = list(x.shape)
+    cap, need = tt_svd_query(dims, x.dtype, max_rank)
+    bufs = [torch.empty(cap[k] * dims[k] * cap[k + 1], dtype=x.dtype, device=x.device) for k in range(len(dims))]
+    ptrs = (c_void_p * len(dims))(*[b.data_ptr() for b in bufs])
+    ranks = (c_int32 * (len(dims) + 1))()
+    ws = _ws(need, x.device)
+    _check(_lib.tt_svd(_ptr(x), len(dims), _i32(dims), _DT[x.dtype], float(eps), int(max_rank), ranks, ptrs,
+                       _ptr(ws), need, _stream(x.device)))
+    r = list(ranks)
+    return [bufs[k][: r[k] * dims[k] * r[k + 1]].view(r[k], dims[k], r[k + 1]) for k in range(len(dims))]
+
+
 def tt_contract_modes_query(x, y, modes, form: str = "junction"):
     dx, dy = TTDesc(x, "x"), TTDesc(y, "y")
     m = _i32(modes)

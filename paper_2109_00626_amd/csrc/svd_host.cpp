@@ -1,0 +1,194 @@
+// Host side of TT-SVD (Algorithm 1): validation, workspace sizing and the
+// N-1 splitting steps.  Each step runs the Jacobi SVD of the running
+// unfolding on the GPU, reads the singular values back (the kept rank
+// depends on them), picks the rank by the delta-truncation rule and splits
+// the unfolding into core k and the next running matrix.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "ttc_internal.h"
+
+namespace ttc {
+ttc_status fail(ttc_status s, const std::string& msg);
+hipError_t launch_svd_transpose(ttc_dtype dt, const void* in, void* out, int m, int n, hipStream_t s);
+hipError_t launch_svd_jacobi(ttc_dtype dt, void* A, void* J, double* sigma, int* info, int p, int L,
+                             int max_sweeps, double tol, hipStream_t s);
+hipError_t launch_svd_split(ttc_dtype dt, const void* A, const void* J, const double* sigma, const int* sel,
+                            int tall, int m, int n, int p, int r, void* G, void* C, hipStream_t s);
+}  // namespace ttc
+using namespace ttc;
+
+#define SVD_TRY(expr)            \
+  do {                           \
+    ttc_status _s = (expr);      \
+    if (_s != TTC_OK) return _s; \
+  } while (0)
+#define SVD_HIP(expr)                                                                                    \
+  do {                                                                                                   \
+    hipError_t _e = (expr);                                                                              \
+    if (_e != hipSuccess) return fail(TTC_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+  } while (0)
+
+namespace {
+
+// Largest number of vectors one Jacobi SVD rotates (min of the unfolding's
+// sides); its p x p rotation matrix and sweeps grow with the square of it.
+const long kMaxSvdVectors = 4096;
+const int kMaxSweeps = 40;
+
+struct SvdPlan {
+  int N = 0;
+  long numel = 1;
+  std::vector<int> cap;  // rank capacity per bond (N + 1)
+  long p_max = 1;
+  size_t es = 8;
+  size_t off_c0 = 0, off_c1 = 0, off_t = 0, off_j = 0, off_sigma = 0, off_sel = 0, off_info = 0, total = 0;
+};
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+ttc_status plan_svd(int32_t order, const int32_t* dims, ttc_dtype dtype, int32_t max_rank, SvdPlan* P) {
+  if (order < 1 || order > TTC_MAX_ORDER) return fail(TTC_ERR_SHAPE, "tt_svd: order outside [1, 32]");
+  if (!dims) return fail(TTC_ERR_NULL, "tt_svd: dims is NULL");
+  if (dtype != TTC_F64 && dtype != TTC_F32) return fail(TTC_ERR_DTYPE, "tt_svd: FP64 or FP32 tensors");
+  P->N = order;
+  P->es = dtype == TTC_F64 ? 8 : 4;
+  P->numel = 1;
+  for (int k = 0; k < order; ++k) {
+    if (dims[k] < 1) return fail(TTC_ERR_SHAPE, "tt_svd: mode size < 1");
+    P->numel *= dims[k];
+    if (P->numel > 2147483647L) return fail(TTC_ERR_UNSUPPORTED, "tt_svd: more than 2^31 - 1 entries");
+  }
+  P->cap.assign(order + 1, 1);
+  long rest = P->numel;
+  P->p_max = 1;
+  for (int k = 0; k + 1 < order; ++k) {
+    const long m = (long)P->cap[k] * dims[k];
+    rest /= dims[k];
+    const long p = std::min(m, rest);
+    P->p_max = std::max(P->p_max, p);
+    long c = p;
+    if (max_rank > 0) c = std::min<long>(c, max_rank);
+    P->cap[k + 1] = (int)c;
+  }
+  if (P->p_max > kMaxSvdVectors)
+    return fail(TTC_ERR_UNSUPPORTED, "tt_svd: an unfolding has more than " + std::to_string(kMaxSvdVectors) +
+                                         " rows and columns (min side " + std::to_string(P->p_max) + ")");
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  P->off_c0 = take(P->numel * P->es);
+  P->off_c1 = take(P->numel * P->es);
+  P->off_t = take(P->numel * P->es);
+  P->off_j = take((size_t)P->p_max * P->p_max * P->es);
+  P->off_sigma = take((size_t)P->p_max * sizeof(double));
+  P->off_sel = take((size_t)P->p_max * sizeof(int));
+  P->off_info = take(2 * sizeof(int));
+  P->total = off;
+  return TTC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ttc_status tt_svd_query(int32_t order, const int32_t* dims, ttc_dtype dtype, int32_t max_rank, int32_t* rank_cap,
+                        size_t* ws_bytes) {
+  SvdPlan P;
+  SVD_TRY(plan_svd(order, dims, dtype, max_rank, &P));
+  if (rank_cap)
+    for (int k = 0; k <= order; ++k) rank_cap[k] = P.cap[k];
+  if (ws_bytes) *ws_bytes = P.total;
+  return TTC_OK;
+}
+
+ttc_status tt_svd(const void* d_x, int32_t order, const int32_t* dims, ttc_dtype dtype, double eps,
+                  int32_t max_rank, int32_t* ranks, void* const* d_cores, void* d_ws, size_t ws_bytes,
+                  void* stream) {
+  SvdPlan P;
+  SVD_TRY(plan_svd(order, dims, dtype, max_rank, &P));
+  if (!d_x) return fail(TTC_ERR_NULL, "tt_svd: d_x is NULL");
+  if (!ranks || !d_cores) return fail(TTC_ERR_NULL, "tt_svd: ranks or d_cores is NULL");
+  for (int k = 0; k < order; ++k)
+    if (!d_cores[k]) return fail(TTC_ERR_NULL, "tt_svd: NULL core buffer");
+  if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(TTC_ERR_SHAPE, "tt_svd: eps must be finite and >= 0");
+  if (P.total > ws_bytes) return fail(TTC_ERR_WORKSPACE, "workspace smaller than tt_svd_query size");
+  if (!d_ws) return fail(TTC_ERR_NULL, "tt_svd: d_ws is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  char* ws = static_cast<char*>(d_ws);
+  void* cur = ws + P.off_c0;
+  void* nxt = ws + P.off_c1;
+  void* tbuf = ws + P.off_t;
+  void* J = ws + P.off_j;
+  double* sigma = reinterpret_cast<double*>(ws + P.off_sigma);
+  int* sel_d = reinterpret_cast<int*>(ws + P.off_sel);
+  int* info_d = reinterpret_cast<int*>(ws + P.off_info);
+  const int N = order;
+  std::vector<int> rk(N + 1, 1);
+  if (N == 1) {
+    SVD_HIP(hipMemcpyAsync(d_cores[0], d_x, P.numel * P.es, hipMemcpyDeviceToDevice, s));
+    ranks[0] = ranks[1] = 1;
+    return TTC_OK;
+  }
+  SVD_HIP(hipMemcpyAsync(cur, d_x, P.numel * P.es, hipMemcpyDeviceToDevice, s));
+  // Jacobi stopping threshold: the rounding level of a dot product of two
+  // rows of length L in the storage precision
+  const double unit = dtype == TTC_F64 ? 1.1102230246251565e-16 : 5.960464477539063e-08;
+  double delta = 0.0;
+  long cur_elems = P.numel;
+  std::vector<double> sg;
+  std::vector<int> order_idx;
+  for (int k = 0; k + 1 < N; ++k) {
+    const long m = (long)rk[k] * dims[k];
+    const long n = cur_elems / m;
+    const bool tall = m > n;
+    const int p = (int)std::min(m, n), L = (int)std::max(m, n);
+    void* A = cur;
+    if (tall) {
+      SVD_HIP(launch_svd_transpose(dtype, cur, tbuf, (int)m, (int)n, s));
+      A = tbuf;
+    }
+    SVD_HIP(launch_svd_jacobi(dtype, A, J, sigma, info_d, p, L, kMaxSweeps, 2.0 * unit * std::sqrt((double)L), s));
+    sg.assign(p, 0.0);
+    SVD_HIP(hipMemcpyAsync(sg.data(), sigma, sizeof(double) * p, hipMemcpyDeviceToHost, s));
+    SVD_HIP(hipStreamSynchronize(s));
+    if (k == 0) {
+      // ||X||_F from the first unfolding's singular values
+      double nx2 = 0;
+      for (double v : sg) nx2 += v * v;
+      delta = eps / std::sqrt((double)(N - 1)) * std::sqrt(nx2);
+    }
+    order_idx.resize(p);
+    std::iota(order_idx.begin(), order_idx.end(), 0);
+    std::stable_sort(order_idx.begin(), order_idx.end(), [&](int a, int b) { return sg[a] > sg[b]; });
+    // smallest r >= 1 whose discarded singular values have norm <= delta
+    std::vector<double> tail(p + 1, 0.0);
+    for (int c = p - 1; c >= 0; --c) tail[c] = tail[c + 1] + sg[order_idx[c]] * sg[order_idx[c]];
+    int r = p;
+    for (int c = 1; c <= p; ++c)
+      if (std::sqrt(tail[c]) <= delta) {
+        r = c;
+        break;
+      }
+    r = std::min(r, P.cap[k + 1]);
+    SVD_HIP(hipMemcpy(sel_d, order_idx.data(), sizeof(int) * r, hipMemcpyHostToDevice));
+    SVD_HIP(launch_svd_split(dtype, A, J, sigma, sel_d, tall ? 1 : 0, (int)m, (int)n, p, r, d_cores[k], nxt, s));
+    rk[k + 1] = r;
+    std::swap(cur, nxt);
+    cur_elems = (long)r * n;
+  }
+  SVD_HIP(hipMemcpyAsync(d_cores[N - 1], cur, cur_elems * P.es, hipMemcpyDeviceToDevice, s));
+  for (int k = 0; k <= N; ++k) ranks[k] = rk[k];
+  return TTC_OK;
+}
+
+}  // extern "C"

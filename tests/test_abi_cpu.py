@@ -207,3 +207,29 @@ def test_layer_schedule_queries(lib, abi):
     inter = 8192 * 512 * 8 * 32 * 4   # bytes of one intermediate
     assert ws["cores", 1] >= 3 * inter + 2 * inter
     assert 2 * inter <= ws["cores", 0] < 3 * inter
+
+
+def test_svd_query_caps_and_errors(lib, abi):
+    dims = (c_int32 * 5)(20, 20, 20, 5, 4)
+    cap = (c_int32 * 6)()
+    need = c_size_t(0)
+    assert lib.tt_svd_query(5, dims, 0, 0, cap, byref(need)) == abi.TTC_OK
+    # bond k can hold at most min(prod of modes left of it, prod right of it)
+    assert list(cap) == [1, 20, 400, 20, 4, 1]
+    assert need.value >= 3 * 160000 * 8 + 400 * 400 * 8
+    assert lib.tt_svd_query(5, dims, 0, 7, cap, byref(need)) == abi.TTC_OK
+    assert list(cap) == [1, 7, 7, 7, 4, 1]
+    assert status_name(abi, lib.tt_svd_query(5, dims, 2, 0, cap, byref(need))) == "TTC_ERR_DTYPE"
+    big = (c_int32 * 2)(5000, 5000)
+    assert status_name(abi, lib.tt_svd_query(2, big, 0, 0, cap, byref(need))) == "TTC_ERR_UNSUPPORTED"
+    zero = (c_int32 * 2)(3, 0)
+    assert status_name(abi, lib.tt_svd_query(2, zero, 0, 0, cap, byref(need))) == "TTC_ERR_SHAPE"
+    ranks = (c_int32 * 6)()
+    cores = (c_void_p * 5)(*[FAKE] * 5)
+    # validation happens before anything touches a pointer
+    assert status_name(abi, lib.tt_svd(None, 5, dims, 0, 0.0, 0, ranks, cores, c_void_p(FAKE), 1 << 40,
+                                       None)) == "TTC_ERR_NULL"
+    assert status_name(abi, lib.tt_svd(c_void_p(FAKE), 5, dims, 0, -1.0, 0, ranks, cores, c_void_p(FAKE), 1 << 40,
+                                       None)) == "TTC_ERR_SHAPE"
+    assert status_name(abi, lib.tt_svd(c_void_p(FAKE), 5, dims, 0, 0.0, 0, ranks, cores, c_void_p(FAKE), 16,
+                                       None)) == "TTC_ERR_WORKSPACE"

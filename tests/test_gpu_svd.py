@@ -1,0 +1,127 @@
+"""GPU parity of TT-SVD (Algorithm 1) against the FP64 oracle, through the C
+ABI: the kept ranks, the cores (a singular vector is fixed only up to its
+sign, so each bond's columns are aligned to the oracle's before the
+comparison, the next core's rows flipped with them), the reconstruction and
+Algorithm 1's error bound, on the paper's Example 2 shapes, truncated
+low-rank tensors, wide and tall unfoldings, and degenerate cases."""
+import numpy as np
+import pytest
+
+from oracle import tt_oracle as O
+from ttgen import configs as C
+
+from helpers import TOL, rel_err, to_np
+
+pytestmark = pytest.mark.gpu
+
+SEED_SVD = C.BASE_SEED + 6
+
+
+def _dense(obj, dims):
+    n = int(np.prod(dims))
+    return C.gen_matrix_np(SEED_SVD, obj, 1, n).reshape(dims)
+
+
+def _upload(X, dtype):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(X)).to(torch.float64 if dtype == "f64" else torch.float32)
+    return t.cuda(), t.to(torch.float64).numpy()
+
+
+def _align(got, want):
+    """Flip each bond's singular-vector signs in `got` to match `want`
+    (column c of core k and row c of core k + 1 together); shapes must
+    match."""
+    got = [g.copy() for g in got]
+    for k in range(len(got) - 1):
+        r = got[k].shape[2]
+        U, Ur = got[k].reshape(-1, r), want[k].reshape(-1, r)
+        sgn = np.sign(np.sum(U * Ur, axis=0))
+        sgn[sgn == 0] = 1.0
+        got[k] = got[k] * sgn[None, None, :]
+        got[k + 1] = got[k + 1] * sgn[:, None, None]
+    return got
+
+
+def _check(ttc, X, dtype, eps, core_tol, max_rank=0):
+    xg, Xs = _upload(X, dtype)
+    cores = [to_np(c) for c in ttc.tt_svd(xg, eps=eps, max_rank=max_rank)]
+    ref = O.tt_svd(Xs, eps)
+    assert [c.shape for c in cores] == [c.shape for c in ref]
+    Xh = O.tt_full(cores)
+    nx = np.linalg.norm(Xs)
+    # Algorithm 1's bound, plus the arithmetic's rounding
+    err = np.linalg.norm(Xh - Xs)
+    assert err <= eps * nx + TOL[dtype] * nx, (err, eps * nx)
+    e = max(rel_err(g, w) for g, w in zip(_align(cores, ref), ref))
+    assert e <= core_tol, e
+    return cores, ref
+
+
+@pytest.mark.parametrize("dims", [(20, 20, 20), (20, 20, 20, 5), (20, 20, 20, 5, 4)])
+def test_svd_example2_shapes_exact(ttc, dims):
+    """The shapes of the paper's Example 2 (Gaussian N(0, 1) entries), eps = 0:
+    full ranks, cores equal to the oracle's up to the sign of each singular
+    vector, reconstruction to FP64 rounding."""
+    X = _dense(1, dims)
+    cores, _ = _check(ttc, X, "f64", 0.0, 1e-9)
+    assert rel_err(O.tt_full(cores), X) <= 1e-12
+
+
+@pytest.mark.parametrize("eps", [1e-4, 3e-2])
+def test_svd_truncates_low_rank_plus_noise(ttc, eps):
+    """A TT of ranks (1, 3, 5, 2, 1) plus noise 1e-7: at eps = 1e-4 both keep
+    exactly those ranks; at eps = 3e-2 the truncation also cuts signal, and
+    the GPU and the oracle still pick the same ranks and cores."""
+    s = C.TTShape([6, 7, 5, 4], [1, 3, 5, 2, 1])
+    X = O.tt_full(C.gen_tt_np(SEED_SVD, 2, s)) + 1e-7 * _dense(3, (6, 7, 5, 4))
+    cores, _ = _check(ttc, X, "f64", eps, 1e-8)
+    if eps == 1e-4:
+        assert [c.shape[0] for c in cores] + [1] == [1, 3, 5, 2, 1]
+
+
+@pytest.mark.parametrize("dims", [(50, 7), (7, 50), (3, 40, 2), (64, 2, 2, 2), (5,)])
+def test_svd_wide_tall_and_small(ttc, dims):
+    """Orders 1-4 with wide (rows <= columns) and tall first unfoldings."""
+    X = _dense(4, dims)
+    _check(ttc, X, "f64", 0.0, 1e-9)
+
+
+def test_svd_rank_one_and_zero(ttc):
+    import torch
+    vs = [C.gen_matrix_np(SEED_SVD, 10 + k, 1, d)[0] for k, d in enumerate((4, 6, 5))]
+    X = np.einsum("a,b,c->abc", *vs)
+    cores, _ = _check(ttc, X, "f64", 1e-10, 1e-9)
+    assert [c.shape[0] for c in cores] == [1, 1, 1]
+    z = torch.zeros(3, 4, 5, dtype=torch.float64, device="cuda")
+    zc = ttc.tt_svd(z)
+    assert [tuple(c.shape) for c in zc] == [(1, 3, 1), (1, 4, 1), (1, 5, 1)]
+    assert all(bool(torch.all(torch.isfinite(c))) for c in zc)
+    assert np.all(O.tt_full([to_np(c) for c in zc]) == 0.0)
+
+
+def test_svd_fp32(ttc):
+    """FP32 tensor, FP32 storage with FP64 dot products: ranks equal the
+    oracle's (on the FP32 values), reconstruction within the FP32 bound,
+    left cores orthonormal."""
+    X = _dense(5, (12, 10, 8, 6))
+    xg, Xs = _upload(X, "f32")
+    cores = [to_np(c) for c in ttc.tt_svd(xg)]
+    ref = O.tt_svd(Xs, 0.0)
+    assert [c.shape for c in cores] == [c.shape for c in ref]
+    assert rel_err(O.tt_full(cores), Xs) <= TOL["f32"]
+    for G in cores[:-1]:
+        U = G.reshape(-1, G.shape[2])
+        assert np.max(np.abs(U.T @ U - np.eye(U.shape[1]))) <= 1e-5
+
+
+def test_svd_max_rank_caps(ttc):
+    X = _dense(6, (8, 9, 10))
+    xg, _ = _upload(X, "f64")
+    cores = ttc.tt_svd(xg, max_rank=3)
+    assert [int(c.shape[0]) for c in cores] + [1] == [1, 3, 3, 1]
+    # the first core is the oracle's first three singular vectors
+    ref = O.tt_svd(X, 0.0)
+    got = to_np(cores[0]).reshape(8, 3)
+    want = ref[0].reshape(8, 8)[:, :3]
+    assert np.max(np.abs(np.abs(np.sum(got * want, axis=0)) - 1.0)) <= 1e-12
