@@ -379,6 +379,104 @@ def contract_dense(x, y, modes) -> np.ndarray:
 
 
 # =========================================================================
+# Contractions of X's modes a1..a2 with Y's modes b1..b2 at any positions
+# (eq. (8) once per pair; Example 1's X x_3^2 Y is a1 = a2 = 2, b1 = b2 = 1)
+# =========================================================================
+def contract_pairs_dense(X: np.ndarray, Y: np.ndarray, xmodes, ymodes) -> np.ndarray:
+    """eq. (8) applied once per pair (X's mode xmodes[l] with Y's ymodes[l]),
+    0-based; output modes: X's free modes, then Y's, each in order."""
+    return np.tensordot(X, Y, axes=(list(xmodes), list(ymodes)))
+
+
+def block_product(cores, lo: int, hi: int) -> np.ndarray:
+    """Cores lo..hi multiplied along their shared bonds (eq. (9)'s product of
+    slices, kept open at both ends): shape (R_lo, I_lo, ..., I_hi, R_{hi+1})."""
+    B = cores[lo]
+    for k in range(lo + 1, hi + 1):
+        B = np.tensordot(B, cores[k], axes=([B.ndim - 1], [0]))
+    return B
+
+
+def transfer_junction(x, y, xmodes, ymodes) -> np.ndarray:
+    """Junction of a contraction over consecutive blocks: with a, b X's bonds
+    before and after its block and g, d Y's,
+      T[(a, g), (b, d)] = sum over the block indices of Xblock[a, i.., b] Yblock[g, i.., d],
+    rows a * |g| + g, columns b * |d| + d.  A prefix block gives W_k, a
+    suffix block V_k (the matrix K of Example 1 / Fig. 3)."""
+    a1, a2 = int(xmodes[0]), int(xmodes[-1])
+    b1, b2 = int(ymodes[0]), int(ymodes[-1])
+    L = a2 - a1 + 1
+    Xb = block_product(x, a1, a2)
+    Yb = block_product(y, b1, b2)
+    T = np.tensordot(Xb, Yb, axes=(list(range(1, L + 1)), list(range(1, L + 1))))  # (a, b, g, d)
+    ka, kb, kg, kd = T.shape
+    return np.transpose(T, (0, 2, 1, 3)).reshape(ka * kg, kb * kd)
+
+
+def contract_pairs_natural(x, y, xmodes, ymodes):
+    """Natural-order TT (eq. (8) mode order) of the contraction over the
+    blocks, with the junction's Y-side indices q = g * |d| + d carried as an
+    extra bond factor (merged index (own bond) * Q + q, Q = |g| |d|):
+      X's cores left of the block are copied (the last absorbs T when X has
+      no cores right of the block: C[s, i, q] = sum_a G[s, i, a] T[(a, g), d]);
+      the first X core right of the block absorbs T:
+        C[a, i, s*Q + q] = sum_b T[(a, g), (b, d)] G[b, i, s];
+      the other X cores right of it: C[(s,q), i, (s',q')] = G[s, i, s'] delta(q, q');
+      Y's cores left of its block carry q; the last of them contracts g:
+        D[(p,q), j, d'] = G[p, j, g] delta(d, d');
+      Y's cores right of its block are copied.
+    X fully contracted: T (|g| x |d|) is absorbed into the last Y core left
+    of the block (D[p, j, d] = sum_g G[p, j, g] T[g, d]), or, with none, into
+    the first core right of it (D[0, j, s] = sum_d T[0, d] G[d, j, s])."""
+    N, M = len(x), len(y)
+    a1, a2 = int(xmodes[0]), int(xmodes[-1])
+    b1, b2 = int(ymodes[0]), int(ymodes[-1])
+    ka, kb = x[a1].shape[0], x[a2].shape[2]
+    kg, kd = y[b1].shape[0], y[b2].shape[2]
+    T4 = transfer_junction(x, y, xmodes, ymodes).reshape(ka, kg, kb, kd)
+    out = []
+    xfree = a1 > 0 or a2 < N - 1
+    if xfree:
+        Q = kg * kd
+        for m in range(a1):
+            G = x[m]
+            if a2 == N - 1 and m == a1 - 1:
+                out.append(np.einsum("sia,agd->sigd", G, T4[:, :, 0, :]).reshape(G.shape[0], G.shape[1], Q))
+            else:
+                out.append(G.copy())
+        for m in range(a2 + 1, N):
+            G = x[m]
+            r0, I, r1 = G.shape
+            if m == a2 + 1:
+                out.append(np.einsum("agbd,bis->aisgd", T4, G).reshape(ka, I, r1 * Q))
+            else:
+                out.append(np.einsum("sit,qu->sqitu", G, np.eye(Q)).reshape(r0 * Q, I, r1 * Q))
+        for m in range(b1):
+            G = y[m]
+            p0, J, p1 = G.shape
+            if m == b1 - 1:
+                D = np.einsum("pjg,de->pgdje", G, np.eye(kd)).reshape(p0 * Q, J, kd)
+            else:
+                D = np.einsum("pjt,qu->pqjtu", G, np.eye(Q)).reshape(p0 * Q, J, p1 * Q)
+            out.append(D)
+        out.extend(G.copy() for G in y[b2 + 1:])
+        return out
+    if b1 == 0 and b2 == M - 1:
+        raise ValueError("every mode of both contracted: the scalar <X, Y>")
+    T = T4[0, :, 0, :]  # (g, d)
+    for m in range(b1):
+        G = y[m]
+        out.append(np.einsum("pjg,gd->pjd", G, T) if m == b1 - 1 else G.copy())
+    for m in range(b2 + 1, M):
+        G = y[m]
+        if b1 == 0 and m == b2 + 1:
+            out.append(np.einsum("d,djs->js", T[0], G)[None])
+        else:
+            out.append(G.copy())
+    return out
+
+
+# =========================================================================
 # Def. 5 on a TT: mode-n product rewrites one core
 # =========================================================================
 def mode_n_tt(x, n: int, A: np.ndarray):

@@ -424,3 +424,86 @@ def test_bf16_rne_against_integer_reference():
     torch = pytest.importorskip("torch")
     t = rng.f32_to_bf16_t(torch.from_numpy(x)).view(torch.int16).numpy().view(np.uint16)
     assert np.array_equal(t, got)
+
+
+# ----------------------------------------- contractions at any positions
+# (eq. (8) once per pair; Example 1's x_3^2 on cores)
+def _tt(seed, obj, modes, ranks):
+    return C.gen_tt_np(seed, obj, C.TTShape(list(modes), list(ranks)))
+
+
+PAIR_CASES = [
+    # (X modes, X ranks, Y modes, Y ranks, xmodes, ymodes)
+    ([3, 4, 5, 2], [1, 2, 3, 2, 1], [3, 5, 4], [1, 2, 3, 1], [2], [1]),          # Example 1: middle / middle
+    ([3, 4, 5, 2], [1, 2, 3, 2, 1], [2, 4, 5, 3], [1, 3, 2, 2, 1], [1, 2], [1, 2]),  # middle blocks of two
+    ([4, 3, 2], [1, 2, 3, 1], [2, 4, 3], [1, 3, 2, 1], [0], [1]),                # X prefix, Y middle
+    ([3, 2, 4], [1, 2, 2, 1], [4, 3, 2], [1, 2, 3, 1], [2], [0]),                # X suffix, Y prefix
+    ([3, 4, 2], [1, 3, 2, 1], [2, 3, 4], [1, 2, 2, 1], [1], [2]),                # X middle, Y suffix
+    ([3, 4], [1, 2, 1], [2, 3, 4, 2], [1, 2, 3, 2, 1], [0, 1], [1, 2]),          # X fully, Y middle
+    ([3, 4], [1, 2, 1], [3, 4, 2], [1, 2, 3, 1], [0, 1], [0, 1]),                # X fully, Y prefix
+    ([3, 4], [1, 2, 1], [2, 3, 4], [1, 2, 3, 1], [0, 1], [1, 2]),                # X fully, Y suffix
+    ([2, 3, 4, 2], [1, 2, 3, 2, 1], [3, 4], [1, 2, 1], [1, 2], [0, 1]),          # Y fully, X middle
+    ([2, 3, 4], [1, 2, 3, 1], [3, 4], [1, 2, 1], [1, 2], [0, 1]),                # Y fully, X suffix
+]
+
+
+def test_contract_pairs_dense_single_pair_is_literal_eq8():
+    rs = np.random.RandomState(31)
+    X = rs.randn(3, 4, 5)
+    Y = rs.randn(5, 2, 4)
+    for n, m in ((2, 0), (1, 2)):
+        assert rel(O.contract_pairs_dense(X, Y, [n], [m]), O.tcp_loops(X, Y, n, m)) < 1e-13
+
+
+def test_contract_pairs_dense_two_pairs_is_eq8_twice():
+    rs = np.random.RandomState(32)
+    X = rs.randn(3, 4, 5, 2)
+    Y = rs.randn(2, 4, 5, 3)
+    Z = O.contract_pairs_dense(X, Y, [1, 2], [1, 2])
+    # eq. (8) on the pair (2, 2), then on the pair that X's mode 1 and Y's mode 1 became
+    Z1 = O.tcp_loops(X, Y, 2, 2)          # modes: X 0,1,3 then Y 0,1,3
+    Z2 = np.trace(Z1, axis1=1, axis2=4)  # X's mode 1 against Y's mode 1
+    assert rel(Z, Z2) < 1e-13
+
+
+@pytest.mark.parametrize("case", PAIR_CASES)
+def test_contract_pairs_natural_reconstructs_eq8(case):
+    mx, rx, my, ry, xm, ym = case
+    x, y = _tt(33, 1, mx, rx), _tt(33, 2, my, ry)
+    nat = O.contract_pairs_natural(x, y, xm, ym)
+    for a, b in zip(nat[:-1], nat[1:]):
+        assert a.shape[2] == b.shape[0]
+    assert nat[0].shape[0] == 1 and nat[-1].shape[2] == 1
+    want = O.contract_pairs_dense(O.tt_full(x), O.tt_full(y), xm, ym)
+    assert rel(O.tt_full(nat), want) < 1e-12
+
+
+def test_transfer_junction_ends_are_the_sweep_interfaces():
+    x, y = small_pair(34, [3, 4, 2, 5], [1, 2, 3, 4, 1], [1, 3, 2, 2, 1])
+    for k in (1, 2, 3):
+        W = O.sweep_lr(x, y, upto=k)[-1]
+        # a prefix block's T is 1 x (R_k P_k): W_k's entries, row-major
+        T = O.transfer_junction(x, y, list(range(k)), list(range(k)))
+        assert T.shape == (1, W.size) and rel(T.reshape(W.shape), W) < 1e-13
+        V = O.sweep_rl(x, y, downto=k)[k]
+        T = O.transfer_junction(x, y, list(range(k, 4)), list(range(k, 4)))
+        assert T.shape == (V.size, 1) and rel(T.reshape(V.shape), V) < 1e-13
+    # the general construction at equal prefix / suffix blocks is the pinned one
+    for modes in ([0, 1], [0], [2, 3], [3]):
+        got = O.contract_pairs_natural(x, y, modes, modes)
+        want = O.contract_natural(x, y, modes)
+        assert len(got) == len(want)
+        assert all(g.shape == w.shape and rel(g, w) < 1e-13 for g, w in zip(got, want))
+
+
+def test_contract_pairs_example1_on_cores_matches_ttcp():
+    with open(os.path.join(GOLD, "example1_shapes.json")) as f:
+        g = json.load(f)
+    sz = g["sizes"]
+    rs = np.random.RandomState(35)
+    X = rs.randn(*[sz[m] for m in g["X_modes"]])
+    Y = rs.randn(*[sz[m] for m in g["Y_modes"]])
+    n, m = g["contract"]["n"] - 1, g["contract"]["m"] - 1
+    Z, _ = O.ttcp(X, Y, n, m)
+    x, y = O.tt_svd(X), O.tt_svd(Y)
+    assert rel(O.tt_full(O.contract_pairs_natural(x, y, [n], [m])), Z) < 1e-12
