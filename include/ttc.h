@@ -261,6 +261,42 @@ ttc_status tt_contract_inner_bwd(const ttc_tt* x, const ttc_tt* y, const double*
                                  void* d_ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Contraction of X's modes xmodes[l] with Y's modes ymodes[l], l < n_pairs
+ * (eq. (8) once per pair, Def. 6; Example 1's X x_n^m Y is n_pairs = 1 at any
+ * n, m).  X and Y may differ in order and in every mode outside the
+ * contracted pairs.  The GPU path takes consecutive increasing blocks on
+ * both sides (xmodes = a1..a2, ymodes = b1..b2) with equal sizes pairwise.
+ * With a, b X's bonds before and after its block and g, d Y's, the blocks
+ * leave the junction
+ *   T[(a, g), (b, d)] = sum over the blocks' indices of X_block[a, .., b] Y_block[g, .., d],
+ * a (R_a P_g) x (R_b P_d) matrix, row a * P_g + g, column b * P_d + d (a
+ * prefix block's T holds W_k, a suffix block's V_k).  Forms:
+ *   JUNCTION:   T to out_junction (FP64 for FP64 inputs, FP32 otherwise);
+ *   NATURAL_TT: the cores of the result in eq. (8)'s mode order (X's free
+ *               modes, then Y's) into out_tt (shapes from the query): X's
+ *               cores left of the block copied, the first X core right of
+ *               it absorbs T and carries q = g * P_d + d (Q = P_g P_d) through
+ *               the rest, Y's cores left of its block carry q and the last of
+ *               them contracts g, Y's cores right of its block copied;
+ *               merged bonds are (own bond) * Q + q;
+ *   DENSE:      the dense result (natural ranks <= 64).
+ * Every position of both contracted: the scalar <X, Y> to out_scalar.  The
+ * transfer runs one core pair at a time, T and its intermediate in the
+ * workspace (each at most 2^28 elements).
+ * tt_contract_pairs_query: out_order, out_modes (host, N + M - 2 n_pairs),
+ * out_ranks (natural: order + 1; junction: the two sides of T), out_elems
+ * and ws_bytes, any may be NULL.
+ * ------------------------------------------------------------------------ */
+ttc_status tt_contract_pairs_query(const ttc_tt* x, const ttc_tt* y, const int32_t* xmodes,
+                                   const int32_t* ymodes, int32_t n_pairs, ttc_form form,
+                                   int32_t* out_order, int32_t* out_modes, int32_t* out_ranks,
+                                   int64_t* out_elems, size_t* ws_bytes);
+ttc_status tt_contract_pairs(const ttc_tt* x, const ttc_tt* y, const int32_t* xmodes,
+                             const int32_t* ymodes, int32_t n_pairs, ttc_form form,
+                             void* out_junction, const ttc_tt* out_tt, void* out_dense,
+                             double* out_scalar, void* d_ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
  * TT-SVD (Algorithm 1): the cores of a dense tensor X (row-major over
  * (i_1, ..., i_N), i_N fastest; FP64 or FP32, computed in that precision with
  * FP64 dot products).  delta = eps / sqrt(N-1) * ||X||_F; for k = 1..N-1 the

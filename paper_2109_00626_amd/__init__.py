@@ -10,6 +10,8 @@ from .api import (  # noqa: F401
     tt_contract_inner_bwd,
     tt_contract_inner_noalloc,
     tt_contract_modes,
+    tt_contract_pairs,
+    tt_contract_pairs_query,
     tt_contract_modes_query,
     tt_mode_n_product,
     tt_svd,

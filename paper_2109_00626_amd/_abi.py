@@ -70,6 +70,10 @@ def _declare(lib):
         "tt_contract_inner_bwd_query": (c_int32, [P(TT), P(TT), c_int32, P(c_size_t)]),
         "tt_contract_inner_bwd": (c_int32, [P(TT), P(TT), c_void_p, P(c_void_p), P(c_void_p), c_int32,
                                             c_void_p, c_size_t, c_void_p]),
+        "tt_contract_pairs_query": (c_int32, [P(TT), P(TT), P(c_int32), P(c_int32), c_int32, c_int32, P(c_int32),
+                                              P(c_int32), P(c_int32), P(c_int64), P(c_size_t)]),
+        "tt_contract_pairs": (c_int32, [P(TT), P(TT), P(c_int32), P(c_int32), c_int32, c_int32, c_void_p, P(TT),
+                                        c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
         "tt_svd_query": (c_int32, [c_int32, P(c_int32), c_int32, c_int32, P(c_int32), P(c_size_t)]),
         "tt_svd": (c_int32, [c_void_p, c_int32, P(c_int32), c_int32, c_double, c_int32, P(c_int32), P(c_void_p),
                              c_void_p, c_size_t, c_void_p]),
@@ -109,6 +113,7 @@ EXPORTED = [
     "ttm_apply_dense_query", "ttm_apply_dense", "ttm_apply_dense_bwd",
     "ttc_mse_loss_query", "ttc_mse_loss",
     "tt_contract_inner_bwd_query", "tt_contract_inner_bwd",
+    "tt_contract_pairs_query", "tt_contract_pairs",
     "tt_svd_query", "tt_svd",
     "tt_batch_plan_create", "tt_batch_plan_info", "tt_batch_plan_config", "tt_batch_run", "tt_batch_run_plain",
     "tt_batch_run_traced",

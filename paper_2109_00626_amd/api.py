@@ -200,6 +200,57 @@ def tt_contract_modes(x, y, modes, form: str = "junction"):
     return Z
 
 
+def tt_contract_pairs_query(x, y, xmodes, ymodes, form: str = "junction"):
+    dx, dy = TTDesc(x, "x"), TTDesc(y, "y")
+    n = len(x) + len(y)
+    order = c_int32(0)
+    om = (c_int32 * (n + 2))()
+    orr = (c_int32 * (n + 3))()
+    elems = c_int64(0)
+    need = c_size_t(0)
+    _check(_lib.tt_contract_pairs_query(dx.ref, dy.ref, _i32(xmodes), _i32(ymodes), len(xmodes), _abi.FORM[form],
+                                        byref(order), om, orr, byref(elems), byref(need)))
+    k = order.value
+    return {"order": k, "modes": list(om[:k]), "ranks": list(orr[:2]) if form == "junction" else list(orr[:k + 1]),
+            "elems": elems.value, "ws": need.value}
+
+
+def tt_contract_pairs(x, y, xmodes, ymodes, form: str = "junction"):
+    """Contraction of X's modes `xmodes` with Y's modes `ymodes` (0-based,
+    pairwise; eq. (8) once per pair).  Returns the scalar when every mode of
+    both is contracted; else the junction T, the natural-order cores, or the
+    dense tensor."""
+    if len(xmodes) != len(ymodes):
+        raise ValueError("one Y mode per X mode")
+    dx, dy = TTDesc(x, "x"), TTDesc(y, "y")
+    q = tt_contract_pairs_query(x, y, xmodes, ymodes, form)
+    dev = dx.device
+    cdt = _comp_dtype(dx.dtype)
+    ws = _ws(q["ws"], dev)
+    xm, ym = _i32(xmodes), _i32(ymodes)
+    f = _abi.FORM[form]
+    st = _stream(dev)
+    n = len(xmodes)
+    if q["order"] == 0:
+        out = torch.empty((), dtype=torch.float64, device=dev)
+        _check(_lib.tt_contract_pairs(dx.ref, dy.ref, xm, ym, n, f, None, None, None, _ptr(out), _ptr(ws), q["ws"],
+                                      st))
+        return out
+    if form == "junction":
+        T = torch.empty(q["ranks"][0], q["ranks"][1], dtype=cdt, device=dev)
+        _check(_lib.tt_contract_pairs(dx.ref, dy.ref, xm, ym, n, f, _ptr(T), None, None, None, _ptr(ws), q["ws"], st))
+        return T
+    if form == "natural":
+        md, rk = q["modes"], q["ranks"]
+        cores = [torch.empty(rk[k], md[k], rk[k + 1], dtype=cdt, device=dev) for k in range(q["order"])]
+        od = TTDesc(cores, "out")
+        _check(_lib.tt_contract_pairs(dx.ref, dy.ref, xm, ym, n, f, None, od.ref, None, None, _ptr(ws), q["ws"], st))
+        return cores
+    Z = torch.empty(*q["modes"], dtype=cdt, device=dev)
+    _check(_lib.tt_contract_pairs(dx.ref, dy.ref, xm, ym, n, f, None, None, _ptr(Z), None, _ptr(ws), q["ws"], st))
+    return Z
+
+
 def tt_mode_n_product(x, modes, mats):
     """X x_n A_n for each (n, A_n); returns the new core list (unchanged cores
     are the input tensors themselves)."""

@@ -40,6 +40,19 @@ __device__ __forceinline__ Tc lift_value(const LiftCore& c, const Tc* K, int Q, 
       const int b = col / Q, qq = col - b * Q;
       return q == qq ? cvt<Tc>(src[((long)a * c.n + i) * c.r1 + b]) : (Tc)0;
     }
+    case LIFT_ABSORB_M: {  // dst (ka, n, r1*Q); row = a, col = s*Q + q, q = g*kd + d
+      const int s = col / Q, q = col - s * Q;
+      const int g = q / c.kd, d = q - g * c.kd;
+      const Tc* T = K + ((long)row * c.kg + g) * c.r0 * c.kd + d;
+      Tc acc = 0;
+      for (int b = 0; b < c.r0; ++b) acc += T[(long)b * c.kd] * cvt<Tc>(src[((long)b * c.n + i) * c.r1 + s]);
+      return acc;
+    }
+    case LIFT_DELTA_SPLIT: {  // dst (r0*Q, n, kd), src (r0, n, kg); row = y*Q + g*kd + d
+      const int y = row / Q, q = row - y * Q;
+      const int g = q / c.kd, d = q - g * c.kd;
+      return d == col ? cvt<Tc>(src[((long)y * c.n + i) * c.r1 + g]) : (Tc)0;
+    }
     default: {  // LIFT_DELTA_LAST: dst (r0*Q, n, 1), src (r0, n, Q)
       const int p = row / Q, q = row - p * Q;
       return cvt<Tc>(src[((long)p * c.n + i) * c.r1 + q]);

@@ -77,11 +77,23 @@ struct GradArgs {
 };
 
 // Natural-order lift of a junction matrix K (see tt_contract_modes).
-enum LiftOp { LIFT_COPY = 0, LIFT_ABSORB_L = 1, LIFT_ABSORB_R = 2, LIFT_DELTA = 3, LIFT_DELTA_LAST = 4 };
+// LIFT_ABSORB_M and LIFT_DELTA_SPLIT serve contractions whose junction has
+// four bonds, T[(a, g), (b, d)] (row-major a, g, b, d; sizes r0 of the core
+// for b, kg for g, kd for d), carried as q = g * kd + d (Q = kg * kd).
+enum LiftOp {
+  LIFT_COPY = 0,
+  LIFT_ABSORB_L = 1,
+  LIFT_ABSORB_R = 2,
+  LIFT_DELTA = 3,
+  LIFT_DELTA_LAST = 4,
+  LIFT_ABSORB_M = 5,     // dst (ka, n, r1 * Q): sum_b T[(a, g), (b, d)] G[b, i, s]
+  LIFT_DELTA_SPLIT = 6   // dst (r0 * Q, n, kd): G[y, i, g] if d == d', src r1 = kg
+};
 struct LiftCore {
   int op;
   int r0, n, r1;     // source core shape
   int d0, d1;        // destination bond sizes (n is shared)
+  int kg, kd;        // LIFT_ABSORB_M / LIFT_DELTA_SPLIT: the carried bond's two factors
   int line_begin;    // first line (d0 x n lines of d1 elements) of this core
   const void* src;
   void* dst;

@@ -233,3 +233,30 @@ def test_svd_query_caps_and_errors(lib, abi):
                                        None)) == "TTC_ERR_SHAPE"
     assert status_name(abi, lib.tt_svd(c_void_p(FAKE), 5, dims, 0, 0.0, 0, ranks, cores, c_void_p(FAKE), 16,
                                        None)) == "TTC_ERR_WORKSPACE"
+
+
+def test_pairs_query_matches_oracle_shapes(lib, abi):
+    """The natural-form shapes the library reports for every block layout
+    equal those of the oracle's construction; the junction is
+    (R_a P_g) x (R_b P_d)."""
+    from test_gpu_pairs import CASES
+    for mx, rx, my, ry, xm, ym in CASES:
+        dx, dy = Desc(abi, mx, rx, 0), Desc(abi, my, ry, 0)
+        n = len(mx) + len(my)
+        order, om, orr = c_int32(0), (c_int32 * n)(), (c_int32 * (n + 1))()
+        elems, need = c_int64(0), c_size_t(0)
+        xa, ya = (c_int32 * len(xm))(*xm), (c_int32 * len(ym))(*ym)
+        assert lib.tt_contract_pairs_query(byref(dx.s), byref(dy.s), xa, ya, len(xm), 1, byref(order), om, orr,
+                                           byref(elems), byref(need)) == abi.TTC_OK
+        x = C.gen_tt_np(1, 1, C.TTShape(mx, rx))
+        y = C.gen_tt_np(1, 2, C.TTShape(my, ry))
+        want = O.contract_pairs_natural(x, y, xm, ym)
+        k = order.value
+        assert k == len(want)
+        assert list(om[:k]) == [w.shape[1] for w in want]
+        assert list(orr[:k + 1]) == [w.shape[0] for w in want] + [1]
+        assert elems.value == sum(w.size for w in want)
+        assert lib.tt_contract_pairs_query(byref(dx.s), byref(dy.s), xa, ya, len(xm), 0, byref(order), om, orr,
+                                           byref(elems), byref(need)) == abi.TTC_OK
+        T = O.transfer_junction(x, y, xm, ym)
+        assert (order.value, orr[0], orr[1]) == (2, T.shape[0], T.shape[1])
