@@ -324,6 +324,26 @@ ttc_status tt_svd(const void* d_x, int32_t order, const int32_t* dims, ttc_dtype
                   void* stream);
 
 /* ------------------------------------------------------------------------
+ * TT-rounding: the rule of Algorithm 1 applied to a TT given by its cores
+ * (FP64 or FP32), without forming the dense tensor.  Right to left, each
+ * core's unfolding (left bond x the rest) is split by the same Jacobi SVD
+ * into orthonormal rows (the new core) and U S, which is multiplied into the
+ * core on its left (exact zero singular values dropped); then left to right,
+ * as in tt_svd, with delta = eps / sqrt(N-1) * ||X||_F and ranks at most
+ * max_rank when max_rank > 0.  The result equals tt_svd of the dense tensor
+ * up to the sign of each singular vector.  tt_round_query: rank_cap (host,
+ * N+1; may be NULL) bounds each output bond, ws_bytes the workspace (N + 1
+ * copies of the largest core, a p x p rotation matrix with p the smaller
+ * side of the widest core unfolding, at most 4096).  tt_round: ranks (host,
+ * N+1) receives the ranks, core k is written (R_k, I_k, R_{k+1}) at the start
+ * of d_cores[k]; the input cores are not modified.  Synchronises `stream`
+ * once per split (2N - 2 times).
+ * ------------------------------------------------------------------------ */
+ttc_status tt_round_query(const ttc_tt* x, int32_t max_rank, int32_t* rank_cap, size_t* ws_bytes);
+ttc_status tt_round(const ttc_tt* x, double eps, int32_t max_rank, int32_t* ranks, void* const* d_cores,
+                    void* d_ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
  * Batched execution: many independent pairs of uneven order, mode sizes and
  * ranks in one persistent launch, replayed from a HIP graph.  For each pair
  * p the right-to-left sweep gives both results:

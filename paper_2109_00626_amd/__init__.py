@@ -14,6 +14,7 @@ from .api import (  # noqa: F401
     tt_contract_pairs_query,
     tt_contract_modes_query,
     tt_mode_n_product,
+    tt_round,
     tt_svd,
     tt_svd_query,
     ttc_mse_loss,

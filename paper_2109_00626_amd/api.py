@@ -149,6 +149,23 @@ def tt_svd(x: torch.Tensor, eps: float = 0.0, max_rank: int = 0):
     return [bufs[k][: r[k] * dims[k] * r[k + 1]].view(r[k], dims[k], r[k + 1]) for k in range(len(dims))]
 
 
+def tt_round(x, eps: float = 0.0, max_rank: int = 0):
+    """TT-rounding of the cores x (FP64 or FP32): list of new cores on x's
+    device, ranks chosen by Algorithm 1's delta rule."""
+    dx = TTDesc(x, "x")
+    n = len(x)
+    cap = (c_int32 * (n + 1))()
+    need = c_size_t(0)
+    _check(_lib.tt_round_query(dx.ref, int(max_rank), cap, byref(need)))
+    bufs = [torch.empty(cap[k] * dx.modes[k] * cap[k + 1], dtype=dx.dtype, device=dx.device) for k in range(n)]
+    ptrs = (c_void_p * n)(*[b.data_ptr() for b in bufs])
+    ranks = (c_int32 * (n + 1))()
+    ws = _ws(need.value, dx.device)
+    _check(_lib.tt_round(dx.ref, float(eps), int(max_rank), ranks, ptrs, _ptr(ws), need.value, _stream(dx.device)))
+    r = list(ranks)
+    return [bufs[k][: r[k] * dx.modes[k] * r[k + 1]].view(r[k], dx.modes[k], r[k + 1]) for k in range(n)]
+
+
 def tt_contract_modes_query(x, y, modes, form: str = "junction"):
     dx, dy = TTDesc(x, "x"), TTDesc(y, "y")
     m = _i32(modes)

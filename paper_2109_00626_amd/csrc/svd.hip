@@ -216,3 +216,79 @@ hipError_t launch_svd_split(ttc_dtype dt, const void* A, const void* J, const do
 }
 
 }  // namespace ttc
+
+namespace ttc {
+
+// C[r, c] = sum_k A[r, k] B[k, c] for row-major A (m x K) and B (K x n); one
+// output per thread, FP64 sums.  The small products of TT-rounding (a core
+// against a rank x rank factor).
+template <typename T>
+__global__ __launch_bounds__(256) void svd_small_gemm_kernel(const T* __restrict__ A, const T* __restrict__ B,
+                                                             T* __restrict__ C, long m, int K, long n) {
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < m * n; e += (long)gridDim.x * blockDim.x) {
+    const long r = e / n, c = e - r * n;
+    const T* a = A + r * K;
+    double acc = 0;
+    for (int k = 0; k < K; ++k) acc += (double)a[k] * (double)B[(long)k * n + c];
+    C[e] = (T)acc;
+  }
+}
+
+// Right-orthogonalisation factors from a converged Jacobi state of an
+// unfolding M (m x n, m = left bond): M = B Q with Q (r x n) orthonormal rows
+// and B = U S (m x r), for the r = min(m, n) singular values in sel:
+//   wide (A = M):    Q[c, :] = A[sel_c, :] / sigma_c;  B[:, c] = sigma_c J[sel_c, :]^T
+//   tall (A = M^T):  Q[c, :] = J[sel_c, :];            B[:, c] = A[sel_c, :]^T
+template <typename T>
+__global__ __launch_bounds__(256) void svd_rsplit_kernel(const T* __restrict__ A, const T* __restrict__ J,
+                                                         const double* __restrict__ sigma,
+                                                         const int* __restrict__ sel, int tall, int m, int n, int p,
+                                                         int r, T* __restrict__ Q, T* __restrict__ B) {
+  const long nq = (long)r * n, nb = (long)m * r;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < nq + nb; e += (long)gridDim.x * blockDim.x) {
+    if (e < nq) {
+      const int c = (int)(e / n), col = (int)(e - (long)c * n);
+      const int q = sel[c];
+      if (!tall) {
+        const double sg = sigma[q];
+        Q[e] = sg > 0 ? (T)((double)A[(long)q * n + col] / sg) : T(0);
+      } else {
+        Q[e] = J[(long)q * p + col];
+      }
+    } else {
+      const long f = e - nq;
+      const int row = (int)(f / r), c = (int)(f - (long)row * r);
+      const int q = sel[c];
+      B[f] = !tall ? (T)(sigma[q] * (double)J[(long)q * p + row]) : A[(long)q * m + row];
+    }
+  }
+}
+
+hipError_t launch_svd_small_gemm(ttc_dtype dt, const void* A, const void* B, void* C, long m, int K, long n,
+                                 hipStream_t s) {
+  const long total = m * n;
+  if (total <= 0) return hipSuccess;
+  const int blocks = (int)std::min<long>((total + 255) / 256, 8192);
+  if (dt == TTC_F64)
+    hipLaunchKernelGGL(svd_small_gemm_kernel<double>, dim3(blocks), dim3(256), 0, s, (const double*)A,
+                       (const double*)B, (double*)C, m, K, n);
+  else
+    hipLaunchKernelGGL(svd_small_gemm_kernel<float>, dim3(blocks), dim3(256), 0, s, (const float*)A,
+                       (const float*)B, (float*)C, m, K, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_svd_rsplit(ttc_dtype dt, const void* A, const void* J, const double* sigma, const int* sel,
+                             int tall, int m, int n, int p, int r, void* Q, void* B, hipStream_t s) {
+  const long total = (long)r * n + (long)m * r;
+  const int blocks = (int)std::min<long>((total + 255) / 256, 4096);
+  if (dt == TTC_F64)
+    hipLaunchKernelGGL(svd_rsplit_kernel<double>, dim3(blocks), dim3(256), 0, s, (const double*)A, (const double*)J,
+                       sigma, sel, tall, m, n, p, r, (double*)Q, (double*)B);
+  else
+    hipLaunchKernelGGL(svd_rsplit_kernel<float>, dim3(blocks), dim3(256), 0, s, (const float*)A, (const float*)J,
+                       sigma, sel, tall, m, n, p, r, (float*)Q, (float*)B);
+  return hipGetLastError();
+}
+
+}  // namespace ttc

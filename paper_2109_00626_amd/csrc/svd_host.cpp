@@ -21,6 +21,10 @@ hipError_t launch_svd_jacobi(ttc_dtype dt, void* A, void* J, double* sigma, int*
                              int max_sweeps, double tol, hipStream_t s);
 hipError_t launch_svd_split(ttc_dtype dt, const void* A, const void* J, const double* sigma, const int* sel,
                             int tall, int m, int n, int p, int r, void* G, void* C, hipStream_t s);
+hipError_t launch_svd_rsplit(ttc_dtype dt, const void* A, const void* J, const double* sigma, const int* sel,
+                             int tall, int m, int n, int p, int r, void* Q, void* B, hipStream_t s);
+hipError_t launch_svd_small_gemm(ttc_dtype dt, const void* A, const void* B, void* C, long m, int K, long n,
+                                 hipStream_t s);
 }  // namespace ttc
 using namespace ttc;
 
@@ -188,6 +192,209 @@ ttc_status tt_svd(const void* d_x, int32_t order, const int32_t* dims, ttc_dtype
   }
   SVD_HIP(hipMemcpyAsync(d_cores[N - 1], cur, cur_elems * P.es, hipMemcpyDeviceToDevice, s));
   for (int k = 0; k <= N; ++k) ranks[k] = rk[k];
+  return TTC_OK;
+}
+
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// TT-rounding: the same delta-truncation applied to a TT given by its cores.
+// Right to left, each core's unfolding (left bond x the rest) is split by
+// the Jacobi SVD into orthonormal rows Q (the new core) and B = U S, which
+// is multiplied into the core on its left; then left to right, exactly as in
+// tt_svd, each core's unfolding is split, core k keeps the left singular
+// vectors and S V^T is multiplied into core k + 1.  After the first pass
+// every core right of the current one is right-orthonormal, so the singular
+// values at each bond are those of the tensor's unfolding there, and the
+// result is what tt_svd gives on the full tensor (up to signs).
+// ---------------------------------------------------------------------------
+namespace {
+
+struct RoundPlan {
+  int N = 0;
+  size_t es = 8;
+  long max_core = 1;
+  long p_max = 1;
+  std::vector<int> cap;
+  size_t off_cores = 0, core_bytes = 0, off_t = 0, off_b = 0, off_j = 0, off_sigma = 0, off_sel = 0, off_info = 0;
+  size_t total = 0;
+};
+
+ttc_status plan_round(const ttc_tt* x, int32_t max_rank, RoundPlan* P) {
+  if (!x) return fail(TTC_ERR_NULL, "tt_round: x is NULL");
+  if (x->order < 1 || x->order > TTC_MAX_ORDER) return fail(TTC_ERR_SHAPE, "tt_round: order outside [1, 32]");
+  if (!x->modes || !x->ranks || !x->cores) return fail(TTC_ERR_NULL, "tt_round: NULL descriptor array");
+  if (x->dtype != TTC_F64 && x->dtype != TTC_F32) return fail(TTC_ERR_DTYPE, "tt_round: FP64 or FP32 cores");
+  const int N = x->order;
+  if (x->ranks[0] != 1 || x->ranks[N] != 1) return fail(TTC_ERR_RANK, "tt_round: boundary ranks must be 1");
+  P->N = N;
+  P->es = x->dtype == TTC_F64 ? 8 : 4;
+  P->max_core = 1;
+  P->p_max = 1;
+  for (int k = 0; k < N; ++k) {
+    if (x->modes[k] < 1 || x->ranks[k] < 1) return fail(TTC_ERR_SHAPE, "tt_round: bad shape");
+    if (!x->cores[k]) return fail(TTC_ERR_NULL, "tt_round: NULL core pointer");
+    const long r0 = x->ranks[k], n = x->modes[k], r1 = x->ranks[k + 1];
+    if ((double)r0 * n * r1 >= 2147483647.0) return fail(TTC_ERR_SHAPE, "tt_round: core too large");
+    P->max_core = std::max(P->max_core, r0 * n * r1);
+    P->p_max = std::max(P->p_max, std::min(r0, n * r1));
+    P->p_max = std::max(P->p_max, std::min(r0 * n, r1));
+  }
+  if (P->p_max > kMaxSvdVectors)
+    return fail(TTC_ERR_UNSUPPORTED, "tt_round: a core unfolding has more than " + std::to_string(kMaxSvdVectors) +
+                                         " rows and columns");
+  // bond capacities: the input rank, and the rank either side's modes allow
+  P->cap.assign(N + 1, 1);
+  double left = 1;
+  for (int k = 1; k < N; ++k) {
+    left *= x->modes[k - 1];
+    double right = 1;
+    for (int j = k; j < N; ++j) right *= x->modes[j];
+    double c = std::min<double>({(double)x->ranks[k], left, right});
+    if (max_rank > 0) c = std::min<double>(c, max_rank);
+    P->cap[k] = (int)c;
+  }
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  P->core_bytes = align256((size_t)P->max_core * P->es);
+  P->off_cores = take(P->core_bytes * (N + 1));  // N working cores and one spare
+  P->off_t = take((size_t)P->max_core * P->es);
+  P->off_b = take((size_t)P->max_core * P->es);
+  P->off_j = take((size_t)P->p_max * P->p_max * P->es);
+  P->off_sigma = take((size_t)P->p_max * sizeof(double));
+  P->off_sel = take((size_t)P->p_max * sizeof(int));
+  P->off_info = take(2 * sizeof(int));
+  P->total = off;
+  return TTC_OK;
+}
+
+// Jacobi SVD of the m x n row-major matrix at M (a transposed copy in tbuf
+// when m > n); singular values returned in decreasing order (sg, order).
+ttc_status svd_of(ttc_dtype dt, void* M, long m, long n, char* ws, const RoundPlan& P, hipStream_t s, void** A,
+                  bool* tall, std::vector<double>& sg, std::vector<int>& order) {
+  const double unit = dt == TTC_F64 ? 1.1102230246251565e-16 : 5.960464477539063e-08;
+  *tall = m > n;
+  const int p = (int)std::min(m, n), L = (int)std::max(m, n);
+  *A = M;
+  if (*tall) {
+    SVD_HIP(launch_svd_transpose(dt, M, ws + P.off_t, (int)m, (int)n, s));
+    *A = ws + P.off_t;
+  }
+  SVD_HIP(launch_svd_jacobi(dt, *A, ws + P.off_j, reinterpret_cast<double*>(ws + P.off_sigma),
+                            reinterpret_cast<int*>(ws + P.off_info), p, L, kMaxSweeps,
+                            2.0 * unit * std::sqrt((double)L), s));
+  sg.assign(p, 0.0);
+  SVD_HIP(hipMemcpyAsync(sg.data(), ws + P.off_sigma, sizeof(double) * p, hipMemcpyDeviceToHost, s));
+  SVD_HIP(hipStreamSynchronize(s));
+  order.resize(p);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return sg[a] > sg[b]; });
+  return TTC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ttc_status tt_round_query(const ttc_tt* x, int32_t max_rank, int32_t* rank_cap, size_t* ws_bytes) {
+  RoundPlan P;
+  SVD_TRY(plan_round(x, max_rank, &P));
+  if (rank_cap)
+    for (int k = 0; k <= x->order; ++k) rank_cap[k] = P.cap[k];
+  if (ws_bytes) *ws_bytes = P.total;
+  return TTC_OK;
+}
+
+ttc_status tt_round(const ttc_tt* x, double eps, int32_t max_rank, int32_t* ranks, void* const* d_cores,
+                    void* d_ws, size_t ws_bytes, void* stream) {
+  RoundPlan P;
+  SVD_TRY(plan_round(x, max_rank, &P));
+  const int N = x->order;
+  if (!ranks || !d_cores) return fail(TTC_ERR_NULL, "tt_round: ranks or d_cores is NULL");
+  for (int k = 0; k < N; ++k)
+    if (!d_cores[k]) return fail(TTC_ERR_NULL, "tt_round: NULL output core");
+  if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(TTC_ERR_SHAPE, "tt_round: eps must be finite and >= 0");
+  if (P.total > ws_bytes) return fail(TTC_ERR_WORKSPACE, "workspace smaller than tt_round_query size");
+  if (!d_ws) return fail(TTC_ERR_NULL, "tt_round: d_ws is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  const ttc_dtype dt = x->dtype;
+  char* ws = static_cast<char*>(d_ws);
+  std::vector<void*> W(N + 1);
+  for (int k = 0; k <= N; ++k) W[k] = ws + P.off_cores + (size_t)k * P.core_bytes;
+  void* spare = W[N];
+  std::vector<int> r(N + 1);
+  for (int k = 0; k <= N; ++k) r[k] = x->ranks[k];
+  for (int k = 0; k < N; ++k)
+    SVD_HIP(hipMemcpyAsync(W[k], x->cores[k], (size_t)r[k] * x->modes[k] * r[k + 1] * P.es,
+                           hipMemcpyDeviceToDevice, s));
+  if (N == 1) {
+    SVD_HIP(hipMemcpyAsync(d_cores[0], W[0], (size_t)x->modes[0] * P.es, hipMemcpyDeviceToDevice, s));
+    ranks[0] = ranks[1] = 1;
+    return TTC_OK;
+  }
+  int* sel_d = reinterpret_cast<int*>(ws + P.off_sel);
+  const double* sigma_d = reinterpret_cast<const double*>(ws + P.off_sigma);
+  void* B = ws + P.off_b;
+  std::vector<double> sg;
+  std::vector<int> order;
+  // right to left: core k = B Q, Q orthonormal rows; B into core k - 1
+  for (int k = N - 1; k >= 1; --k) {
+    const long m = r[k], n = (long)x->modes[k] * r[k + 1];
+    void* A = nullptr;
+    bool tall = false;
+    SVD_TRY(svd_of(dt, W[k], m, n, ws, P, s, &A, &tall, sg, order));
+    int rk = 0;
+    for (double v : sg) rk += v > 0 ? 1 : 0;
+    rk = std::max(rk, 1);
+    SVD_HIP(hipMemcpy(sel_d, order.data(), sizeof(int) * rk, hipMemcpyHostToDevice));
+    const int p = (int)std::min(m, n);
+    SVD_HIP(launch_svd_rsplit(dt, A, ws + P.off_j, sigma_d, sel_d, tall ? 1 : 0, (int)m, (int)n, p, rk, spare, B, s));
+    std::swap(W[k], spare);
+    // core k - 1 (R_{k-1} I_{k-1} x R_k) times B (R_k x rk)
+    const long lm = (long)r[k - 1] * x->modes[k - 1];
+    SVD_HIP(launch_svd_small_gemm(dt, W[k - 1], B, spare, lm, (int)m, rk, s));
+    std::swap(W[k - 1], spare);
+    r[k] = rk;
+  }
+  // left to right: the delta-truncated splits of tt_svd
+  double delta = 0.0;
+  for (int k = 0; k + 1 < N; ++k) {
+    const long m = (long)r[k] * x->modes[k], n = r[k + 1];
+    void* A = nullptr;
+    bool tall = false;
+    SVD_TRY(svd_of(dt, W[k], m, n, ws, P, s, &A, &tall, sg, order));
+    const int p = (int)std::min(m, n);
+    if (k == 0) {
+      double nx2 = 0;
+      for (double v : sg) nx2 += v * v;
+      delta = eps / std::sqrt((double)(N - 1)) * std::sqrt(nx2);
+    }
+    std::vector<double> tail(p + 1, 0.0);
+    for (int c = p - 1; c >= 0; --c) tail[c] = tail[c + 1] + sg[order[c]] * sg[order[c]];
+    int rk = p;
+    for (int c = 1; c <= p; ++c)
+      if (std::sqrt(tail[c]) <= delta) {
+        rk = c;
+        break;
+      }
+    rk = std::min(rk, P.cap[k + 1]);
+    SVD_HIP(hipMemcpy(sel_d, order.data(), sizeof(int) * rk, hipMemcpyHostToDevice));
+    // core k = U_rk (into the caller's buffer), S V^T (rk x R_{k+1}) into B
+    SVD_HIP(launch_svd_split(dt, A, ws + P.off_j, sigma_d, sel_d, tall ? 1 : 0, (int)m, (int)n, p, rk, d_cores[k], B,
+                             s));
+    const long rn = (long)x->modes[k + 1] * r[k + 2];
+    SVD_HIP(launch_svd_small_gemm(dt, B, W[k + 1], spare, rk, (int)n, rn, s));
+    std::swap(W[k + 1], spare);
+    r[k + 1] = rk;
+  }
+  SVD_HIP(hipMemcpyAsync(d_cores[N - 1], W[N - 1], (size_t)r[N - 1] * x->modes[N - 1] * P.es,
+                         hipMemcpyDeviceToDevice, s));
+  for (int k = 0; k <= N; ++k) ranks[k] = r[k];
   return TTC_OK;
 }
 

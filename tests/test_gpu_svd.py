@@ -125,3 +125,78 @@ def test_svd_max_rank_caps(ttc):
     got = to_np(cores[0]).reshape(8, 3)
     want = ref[0].reshape(8, 8)[:, :3]
     assert np.max(np.abs(np.abs(np.sum(got * want, axis=0)) - 1.0)) <= 1e-12
+
+
+# ------------------------------------------------------------ TT-rounding
+def _tt_sum(x, y):
+    """Cores of X + Y (block-diagonal middle cores, concatenated ends): a
+    valid TT with the ranks added, used as redundant input to rounding."""
+    N = len(x)
+    out = []
+    for k in range(N):
+        a, b = x[k], y[k]
+        if k == 0:
+            out.append(np.concatenate([a, b], axis=2))
+        elif k == N - 1:
+            out.append(np.concatenate([a, b], axis=0))
+        else:
+            G = np.zeros((a.shape[0] + b.shape[0], a.shape[1], a.shape[2] + b.shape[2]))
+            G[:a.shape[0], :, :a.shape[2]] = a
+            G[a.shape[0]:, :, a.shape[2]:] = b
+            out.append(G)
+    return out
+
+
+def _round_check(ttc, x, eps, dtype="f64", core_tol=1e-9, max_rank=0):
+    from helpers import to_gpu
+    xg, xs = to_gpu(x, dtype)
+    cores = [to_np(c) for c in ttc.tt_round(xg, eps=eps, max_rank=max_rank)]
+    Xs = O.tt_full(xs)
+    ref = O.tt_svd(Xs, eps)
+    assert [c.shape for c in cores] == [c.shape for c in ref]
+    nx = np.linalg.norm(Xs)
+    assert np.linalg.norm(O.tt_full(cores) - Xs) <= eps * nx + TOL[dtype] * nx
+    if core_tol is not None:
+        assert max(rel_err(g, w) for g, w in zip(_align(cores, ref), ref)) <= core_tol
+    return cores
+
+
+def test_round_recovers_ranks_of_a_redundant_sum(ttc):
+    """X + X held with doubled ranks: rounding at eps = 1e-10 returns the
+    ranks of X and the cores of TT-SVD of the dense 2X."""
+    s = C.TTShape([5, 6, 4, 3], [1, 3, 4, 2, 1])
+    x = C.gen_tt_np(SEED_SVD, 20, s)
+    cores = _round_check(ttc, _tt_sum(x, x), 1e-10)
+    assert [c.shape[0] for c in cores] + [1] == [1, 3, 4, 2, 1]
+
+
+@pytest.mark.parametrize("eps", [1e-12, 0.05, 0.3])
+def test_round_truncates_like_tt_svd(ttc, eps):
+    """eps 1e-12: the exact ranks (the dense tensor's rounding-level
+    singular values, about 1e-16, fall below delta); larger eps truncate
+    signal, and the ranks and cores follow TT-SVD of the dense tensor."""
+    s = C.TTShape([4, 5, 6, 3], [1, 4, 8, 3, 1])
+    x = C.gen_tt_np(SEED_SVD, 21, s)
+    _round_check(ttc, x, eps)
+
+
+def test_round_mpo_product(ttc):
+    """The MPO x TT output (ranks multiplied, 3 x 4 = 12) rounded back."""
+    from helpers import to_gpu
+    sw = C.TTShape([4, 3, 4, 2], [1, 3, 3, 3, 1], [3, 4, 2, 3])
+    sv = C.TTShape([3, 4, 2, 3], [1, 4, 4, 4, 1])
+    wg, _ = to_gpu(C.gen_tt_np(SEED_SVD, 22, sw), "f64")
+    vg, _ = to_gpu(C.gen_tt_np(SEED_SVD, 23, sv), "f64")
+    out = [to_np(t) for t in ttc.ttm_apply(wg, vg)]
+    assert [c.shape[0] for c in out][1:] == [12, 12, 12]
+    _round_check(ttc, out, 1e-8)
+
+
+def test_round_fp32_and_cap(ttc):
+    s = C.TTShape([4, 5, 6, 3], [1, 4, 8, 3, 1])
+    x = C.gen_tt_np(SEED_SVD, 24, s)
+    _round_check(ttc, x, 1e-6, dtype="f32", core_tol=None)
+    from helpers import to_gpu
+    xg, _ = to_gpu(x, "f64")
+    cores = ttc.tt_round(xg, max_rank=2)
+    assert [int(c.shape[0]) for c in cores] + [1] == [1, 2, 2, 2, 1]
