@@ -375,6 +375,18 @@ typedef struct ttc_plan ttc_plan;
 
 ttc_status tt_batch_plan_create(const ttc_pair* pairs, int32_t n, uint32_t ops, ttc_prec prec,
                                 ttc_plan** plan);
+/* The plan's host-side bookkeeping without creating a plan (no device
+ * call): the same validation as tt_batch_plan_create; junction_offsets (n+1
+ * int64: prefix sums of R_{N-2} P_{N-2} per pair with SUFFIX2, else zeros),
+ * the algorithmic FLOPs (the cheaper contraction order of every
+ * right-to-left step, the first cores' product and the final sum) and bytes
+ * (every core read once, the FP64 scalar and the FP32 junction written once)
+ * of one run, each pair's modelled cost (shader cycles of one workgroup) and
+ * claim_order (n int32: pairs by decreasing cost, ties in index order, the
+ * order in which the LDS-resident schedules' workgroups claim them).  Every
+ * output is a host array and may be NULL. */
+ttc_status tt_batch_plan_query(const ttc_pair* pairs, int32_t n, uint32_t ops, int64_t* junction_offsets,
+                               double* flops, double* bytes, double* cost, int32_t* claim_order);
 /* junction_offsets: host array of n+1 int64 (may be NULL); flops / bytes:
  * algorithmic FLOPs and bytes of one run (may be NULL). */
 ttc_status tt_batch_plan_info(const ttc_plan* plan, int64_t* junction_offsets, double* flops,

@@ -80,6 +80,8 @@ def _declare(lib):
         "tt_round_query": (c_int32, [P(TT), c_int32, P(c_int32), P(c_size_t)]),
         "tt_round": (c_int32, [P(TT), c_double, c_int32, P(c_int32), P(c_void_p), c_void_p, c_size_t, c_void_p]),
         "tt_batch_plan_create": (c_int32, [P(Pair), c_int32, c_uint32, c_int32, P(c_void_p)]),
+        "tt_batch_plan_query": (c_int32, [P(Pair), c_int32, c_uint32, P(c_int64), P(c_double), P(c_double),
+                                          P(c_double), P(c_int32)]),
         "tt_batch_plan_info": (c_int32, [c_void_p, P(c_int64), P(c_double), P(c_double)]),
         "tt_batch_plan_config": (c_int32, [c_void_p, P(c_int32), P(c_int32), P(c_int32)]),
         "tt_batch_run": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
@@ -117,7 +119,7 @@ EXPORTED = [
     "tt_contract_inner_bwd_query", "tt_contract_inner_bwd",
     "tt_contract_pairs_query", "tt_contract_pairs",
     "tt_svd_query", "tt_svd", "tt_round_query", "tt_round",
-    "tt_batch_plan_create", "tt_batch_plan_info", "tt_batch_plan_config", "tt_batch_run", "tt_batch_run_plain",
+    "tt_batch_plan_create", "tt_batch_plan_query", "tt_batch_plan_info", "tt_batch_plan_config", "tt_batch_run", "tt_batch_run_plain",
     "tt_batch_run_traced",
     "tt_batch_plan_destroy",
 ]

@@ -206,6 +206,46 @@ double pair_time_model(const PairHost& h) {
   return t + 10000.0;
 }
 
+// Per-pair sizes of one run: junction elements (R_{N-2} P_{N-2} with
+// SUFFIX2), algorithmic FLOPs (the cheaper order of every right-to-left
+// step, then the first cores' product and the final sum) and algorithmic
+// bytes (every core read once, the FP64 scalar and the FP32 junction
+// written once).
+void pair_measures(const PairHost& h, uint32_t ops, size_t esz, int64_t* jlen, double* flops, double* bytes) {
+  const int N = h.order;
+  *jlen = (ops & TTC_OP_SUFFIX2) ? (int64_t)h.rx[N - 2] * h.ry[N - 2] : 0;
+  double fl = 0, by = 0;
+  for (int k = 1; k < N; ++k) fl += step_flops(h, k);
+  fl += 2.0 * h.modes[0] * h.rx[1] * h.ry[1] + 2.0 * h.rx[1] * h.ry[1];
+  for (int k = 0; k < N; ++k)
+    by += (double)esz * ((double)h.rx[k] * h.modes[k] * h.rx[k + 1] + (double)h.ry[k] * h.modes[k] * h.ry[k + 1]);
+  by += (ops & TTC_OP_INNER) ? 8.0 : 0.0;
+  by += 4.0 * (double)*jlen;
+  *flops = fl;
+  *bytes = by;
+}
+
+PairHost host_pair(const ttc_pair& p) {
+  PairHost h;
+  const int N = p.x.order;
+  h.order = N;
+  h.modes.assign(p.x.modes, p.x.modes + N);
+  h.rx.assign(p.x.ranks, p.x.ranks + N + 1);
+  h.ry.assign(p.y.ranks, p.y.ranks + N + 1);
+  h.xc.assign(p.x.cores, p.x.cores + N);
+  h.yc.assign(p.y.cores, p.y.cores + N);
+  return h;
+}
+
+// Pair indices by decreasing modelled cost, ties in index order: the order in
+// which the LDS-resident kernels' workgroups claim pairs.
+std::vector<int> longest_first(const std::vector<double>& cost) {
+  std::vector<int> idx(cost.size());
+  for (size_t i = 0; i < idx.size(); ++i) idx[i] = (int)i;
+  std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+  return idx;
+}
+
 // Static longest-processing-time assignment: pairs sorted by cost, each
 // given to the currently least-loaded workgroup.  Returns CSR lists.
 void lpt_assign(const std::vector<double>& cost, int grid, std::vector<int>* begin, std::vector<int>* order) {
@@ -324,12 +364,7 @@ ttc_status upload_assignment(ttc_plan* P, const LaunchCfg& c, int* grid_out, int
   const int grid = std::min(P->cus * c.per_cu, std::max(P->n, 1));
   std::vector<int> begin, order;
   lpt_assign(P->cost, grid, &begin, &order);
-  if (lds_mode(c.mode)) {
-    // claimed one by one at run time: the whole list, longest first
-    order.resize(P->n);
-    for (int i = 0; i < P->n; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return P->cost[a] > P->cost[b]; });
-  }
+  if (lds_mode(c.mode)) order = longest_first(P->cost);  // claimed one by one at run time
   TTC_HIP(hipMemcpy(P->d_begin, begin.data(), begin.size() * sizeof(int), hipMemcpyHostToDevice));
   TTC_HIP(hipMemcpy(P->d_order, order.data(), order.size() * sizeof(int), hipMemcpyHostToDevice));
   *grid_out = grid;
@@ -560,14 +595,10 @@ ttc_status tt_batch_plan_create(const ttc_pair* pairs, int32_t n, uint32_t ops, 
     ipool.insert(ipool.end(), h.ry.begin(), h.ry.end());
     ppool.insert(ppool.end(), h.xc.begin(), h.xc.end());
     ppool.insert(ppool.end(), h.yc.begin(), h.yc.end());
-    P->joff[i + 1] = P->joff[i] + ((ops & TTC_OP_SUFFIX2) ? (int64_t)h.rx[N - 2] * h.ry[N - 2] : 0);
+    int64_t jlen = 0;
     double fl = 0, by = 0;
-    for (int k = 1; k < N; ++k) fl += step_flops(h, k);
-    fl += 2.0 * h.modes[0] * h.rx[1] * h.ry[1] + 2.0 * h.rx[1] * h.ry[1];
-    for (int k = 0; k < N; ++k)
-      by += (double)esz * ((double)h.rx[k] * h.modes[k] * h.rx[k + 1] + (double)h.ry[k] * h.modes[k] * h.ry[k + 1]);
-    by += (ops & TTC_OP_INNER) ? 8.0 : 0.0;
-    by += 4.0 * (double)(P->joff[i + 1] - P->joff[i]);
+    pair_measures(h, ops, esz, &jlen, &fl, &by);
+    P->joff[i + 1] = P->joff[i] + jlen;
     P->flops += fl;
     P->bytes += by;
     P->cost[i] = pair_time_model(h);
@@ -729,6 +760,38 @@ ttc_status tt_batch_plan_create(const ttc_pair* pairs, int32_t n, uint32_t ops, 
     return st;
   }
   *plan = P;
+  return TTC_OK;
+}
+
+ttc_status tt_batch_plan_query(const ttc_pair* pairs, int32_t n, uint32_t ops, int64_t* junction_offsets,
+                               double* flops, double* bytes, double* cost, int32_t* claim_order) {
+  if (!pairs || n < 1) return fail(TTC_ERR_NULL, "no pairs");
+  if (ops == 0 || (ops & ~(TTC_OP_INNER | TTC_OP_SUFFIX2))) return fail(TTC_ERR_UNSUPPORTED, "bad ops mask");
+  ttc_dtype dt = TTC_F32;
+  for (int i = 0; i < n; ++i) TTC_TRY(check_pair_desc(pairs[i], i, ops, &dt));
+  const size_t esz = dt == TTC_BF16 ? 2 : 4;
+  std::vector<double> c(n);
+  int64_t off = 0;
+  double tf = 0, tb = 0;
+  if (junction_offsets) junction_offsets[0] = 0;
+  for (int i = 0; i < n; ++i) {
+    const PairHost h = host_pair(pairs[i]);
+    int64_t jlen = 0;
+    double fl = 0, by = 0;
+    pair_measures(h, ops, esz, &jlen, &fl, &by);
+    off += jlen;
+    tf += fl;
+    tb += by;
+    c[i] = pair_time_model(h);
+    if (junction_offsets) junction_offsets[i + 1] = off;
+    if (cost) cost[i] = c[i];
+  }
+  if (flops) *flops = tf;
+  if (bytes) *bytes = tb;
+  if (claim_order) {
+    const std::vector<int> idx = longest_first(c);
+    for (int i = 0; i < n; ++i) claim_order[i] = idx[i];
+  }
   return TTC_OK;
 }
 

@@ -260,3 +260,69 @@ def test_pairs_query_matches_oracle_shapes(lib, abi):
                                            byref(elems), byref(need)) == abi.TTC_OK
         T = O.transfer_junction(x, y, xm, ym)
         assert (order.value, orr[0], orr[1]) == (2, T.shape[0], T.shape[1])
+
+
+def _pairs_array(abi, shapes, dtype=1):
+    descs = [(Desc(abi, sx.modes, sx.ranks, dtype), Desc(abi, sy.modes, sy.ranks, dtype)) for sx, sy in shapes]
+    arr = (abi.Pair * len(shapes))(*[abi.Pair(dx.s, dy.s) for dx, dy in descs])
+    return arr, descs
+
+
+def test_batch_plan_query_against_rederivation(lib, abi):
+    """The batch planner's host bookkeeping on 300 pairs of the uneven
+    workload's distribution, re-derived here: junction offsets, algorithmic
+    FLOPs (the cheaper order of each right-to-left step) and bytes, and the
+    claim order (decreasing modelled cost, ties by index)."""
+    shapes = C.batch_pair_shapes(C.SEED_BATCH, 300)
+    arr, keep = _pairs_array(abi, shapes)
+    n = len(shapes)
+    joff, cost, order = (c_int64 * (n + 1))(), (ctypes.c_double * n)(), (c_int32 * n)()
+    fl, by = ctypes.c_double(0), ctypes.c_double(0)
+    assert lib.tt_batch_plan_query(arr, n, 3, joff, byref(fl), byref(by), cost, order) == abi.TTC_OK
+    want_off, want_fl, want_by = [0], 0.0, 0.0
+    for sx, sy in shapes:
+        N, I, R, P = sx.order, sx.modes, sx.ranks, sy.ranks
+        want_off.append(want_off[-1] + R[N - 2] * P[N - 2])
+        for k in range(1, N):
+            a = 2 * I[k] * R[k] * P[k + 1] * (R[k + 1] + P[k])
+            b = 2 * I[k] * R[k + 1] * P[k] * (P[k + 1] + R[k])
+            want_fl += min(a, b)
+        want_fl += 2 * I[0] * R[1] * P[1] + 2 * R[1] * P[1]
+        want_by += 4 * sum(R[k] * I[k] * R[k + 1] + P[k] * I[k] * P[k + 1] for k in range(N)) + 8
+        want_by += 4 * R[N - 2] * P[N - 2]
+    assert list(joff) == want_off
+    assert fl.value == pytest.approx(want_fl, rel=1e-12)
+    assert by.value == pytest.approx(want_by, rel=1e-12)
+    c = np.array(list(cost))
+    assert np.all(c > 0)
+    assert list(order) == list(np.argsort(-c, kind="stable"))
+    # a pair's modelled cost grows with its ranks and its order
+    sx, sy = C.TTShape([16] * 6, [1] + [32] * 5 + [1]), C.TTShape([16] * 6, [1] + [32] * 5 + [1])
+    sx2, sy2 = C.TTShape([16] * 6, [1] + [64] * 5 + [1]), C.TTShape([16] * 6, [1] + [64] * 5 + [1])
+    sx3, sy3 = C.TTShape([16] * 9, [1] + [32] * 8 + [1]), C.TTShape([16] * 9, [1] + [32] * 8 + [1])
+    arr, keep = _pairs_array(abi, [(sx, sy), (sx2, sy2), (sx3, sy3)])
+    cost3 = (ctypes.c_double * 3)()
+    assert lib.tt_batch_plan_query(arr, 3, 3, None, None, None, cost3, None) == abi.TTC_OK
+    assert cost3[1] > cost3[0] and cost3[2] > cost3[0]
+
+
+def test_batch_plan_query_errors(lib, abi):
+    ok = (C.TTShape([4, 5, 6], [1, 3, 2, 1]), C.TTShape([4, 5, 6], [1, 2, 2, 1]))
+    cases = [
+        ([ok], 0, "TTC_ERR_UNSUPPORTED"),                                                  # no ops
+        ([(C.TTShape([4, 5, 6], [1, 200, 2, 1]), ok[1])], 3, "TTC_ERR_UNSUPPORTED"),       # rank > 128
+        ([(ok[0], C.TTShape([4, 5, 7], [1, 2, 2, 1]))], 3, "TTC_ERR_SHAPE"),               # modes differ
+        ([(C.TTShape([4, 5], [1, 3, 1]), C.TTShape([4, 5], [1, 2, 1]))], 3, "TTC_ERR_SHAPE"),  # SUFFIX2 at order 2
+        ([(ok[0], C.TTShape([4, 5, 6], [1, 2, 2, 2]))], 3, "TTC_ERR_RANK"),                # boundary rank
+    ]
+    for shapes, ops, want in cases:
+        arr, keep = _pairs_array(abi, shapes)
+        assert status_name(abi, lib.tt_batch_plan_query(arr, len(shapes), ops, None, None, None, None, None)) == want
+    # order 2 is fine for the inner product alone
+    arr, keep = _pairs_array(abi, [(C.TTShape([4, 5], [1, 3, 1]), C.TTShape([4, 5], [1, 2, 1]))])
+    assert lib.tt_batch_plan_query(arr, 1, 1, None, None, None, None, None) == abi.TTC_OK
+    # one dtype per batch
+    dx, dy = Desc(abi, [4, 5, 6], [1, 3, 2, 1], 1), Desc(abi, [4, 5, 6], [1, 2, 2, 1], 1)
+    ex, ey = Desc(abi, [4, 5, 6], [1, 3, 2, 1], 2), Desc(abi, [4, 5, 6], [1, 2, 2, 1], 2)
+    arr = (abi.Pair * 2)(abi.Pair(dx.s, dy.s), abi.Pair(ex.s, ey.s))
+    assert status_name(abi, lib.tt_batch_plan_query(arr, 2, 3, None, None, None, None, None)) == "TTC_ERR_DTYPE"
