@@ -216,6 +216,44 @@ def measured_peaks(W, stream):
     return out
 
 
+# ------------------------------------------------------------- Example 2
+EX2_DIMS = [(20, 20, 20), (20, 20, 20, 5), (20, 20, 20, 5, 4)]
+SEED_EX2 = 210900626 + 7
+
+
+def example2_inputs(dims, device, dtype):
+    """Gaussian N(0, 1) tensors X and Y of shape `dims` (the paper's Example 2)."""
+    from ttgen import configs as C
+    n = int(math.prod(dims))
+    X = C.gen_matrix_torch(SEED_EX2, 1, 1, n, device, dtype).reshape(dims)
+    Y = C.gen_matrix_torch(SEED_EX2, 2, 1, n, device, dtype).reshape(dims)
+    return X, Y
+
+
+def example2_gpu(ttc, reps=3):
+    """Example 2 on the GPU: TTCP of X x_1^1 Y from dense inputs, i.e. TT-SVD
+    of both (Algorithm 1, eps = 0) and the contraction of their first cores
+    (the junction K and the free cores), wall time per run (the TT-SVD reads
+    singular values back once per split)."""
+    import torch
+    out = {}
+    for dims in EX2_DIMS:
+        X, Y = example2_inputs(dims, "cuda", torch.float64)
+        ts = []
+        for _ in range(reps + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            gx = ttc.tt_svd(X)
+            gy = ttc.tt_svd(Y)
+            K = ttc.tt_contract_pairs(gx, gy, [0], [0], "junction")
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        out["x".join(map(str, dims))] = {"ttcp_ms": round(1e3 * sorted(ts[1:])[len(ts[1:]) // 2], 3),
+                                        "ranks_x": [int(g.shape[0]) for g in gx] + [1],
+                                        "K_shape": [int(K.shape[0]), int(K.shape[1])]}
+    return out
+
+
 # ------------------------------------------------------------- CPU baseline
 def cpu_baseline(W, n_contr, budget_s=20.0):
     """The FP64 oracle as it is, on a bounded sample of each part, each part's
@@ -303,6 +341,17 @@ def cpu_baseline(W, n_contr, budget_s=20.0):
         est["layer4"] = t_fixed + t_rows * (8192 / rows)
         sample.append(f"layer4: {rows} of 8192 rows (row-proportional work scaled by {8192 // rows}, "
                       "reconstruction and projection once)")
+    # Example 2 on the host: the oracle's dense eq. (8) and its TTCP
+    # (Algorithm 2 with TT-SVD), on the same Gaussian tensors
+    ex2 = {}
+    for dims in EX2_DIMS:
+        X, Y = (t.numpy() for t in example2_inputs(dims, "cpu", torch.float64))
+        t0 = time.perf_counter()
+        O.tcp(X, Y, 0, 0)
+        t1 = time.perf_counter()
+        O.ttcp(X, Y, 0, 0)
+        t2 = time.perf_counter()
+        ex2["x".join(map(str, dims))] = {"dense_tcp_ms": round(1e3 * (t1 - t0), 3), "ttcp_ms": round(1e3 * (t2 - t1), 3)}
     total = sum(est.values())
     threads = os.cpu_count()
     try:
@@ -320,6 +369,7 @@ def cpu_baseline(W, n_contr, budget_s=20.0):
         "sample": "; ".join(sample) + f"; measured {time.perf_counter() - t_all:.1f} s, estimated full step "
                                       f"{total:.2f} s",
         "est_seconds_per_part": {k: round(v, 4) for k, v in est.items()},
+        "example2": ex2,
     }
 
 
@@ -513,6 +563,9 @@ def main():
             Q = int(np.prod(sh.modes[:k])) if k > 0 else 1
             fl += 2.0 * P * Q * sh.cols[k] * sh.ranks[k] * sh.modes[k] * sh.ranks[k + 1]
         beside["layer4_cores_f32_fwd_TFLOPs"] = round(fl / (beside["layer4_cores_f32_fwd_ms"] * 1e-3) / 1e12, 2)
+
+    if not args.no_beside:
+        beside["example2"] = example2_gpu(ttc)
 
     line = {
         "metric": "TT contractions/s + achieved GB/s or TFLOP/s vs roofline; fwd+bwd ms, plain vs batched",

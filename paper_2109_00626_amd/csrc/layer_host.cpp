@@ -71,9 +71,20 @@ struct LayerPlan {
   float* RA = nullptr;             // right-environment ping-pong
   float* RB = nullptr;
   float* slab = nullptr;
+  // BF16 operand copies for the 256 x 256-tile BF16 products (when used)
+  uint16_t* A16 = nullptr;         // X or dY, k contiguous
+  uint16_t* B16 = nullptr;         // W or W^T
+  uint16_t* C16 = nullptr;         // dY^T
+  uint16_t* D16 = nullptr;         // X^T
 };
 
-void plan_layer(const ttc_ttm* m, bool backward, Arena& a, LayerPlan* p) {
+// A product goes to the BF16 tile kernel when its reduction length is a
+// multiple of 8 and it has enough 256 x 256 tiles to fill the GPU.
+bool use_gemm16(long M, long N, long K) {
+  return K % 8 == 0 && ((M + 255) / 256) * ((N + 255) / 256) >= 64;
+}
+
+void plan_layer(const ttc_ttm* m, bool backward, bool bf16, long batch, Arena& a, LayerPlan* p) {
   const int d = m->order;
   p->d = d;
   p->rows = 1;
@@ -96,6 +107,44 @@ void plan_layer(const ttc_ttm* m, bool backward, Arena& a, LayerPlan* p) {
     p->RB = a.take((size_t)mx);
   }
   p->slab = a.take(kSlabElems);
+  if (bf16) {
+    auto take16 = [&](long n) { return reinterpret_cast<uint16_t*>(a.take((size_t)(n + 1) / 2)); };
+    const bool fwd16 = use_gemm16(batch, p->rows, p->cols);
+    const bool dx16 = backward && use_gemm16(batch, p->cols, p->rows);
+    const bool dw16 = backward && use_gemm16(p->rows, p->cols, batch);
+    if (fwd16 || dx16) {
+      p->A16 = take16(batch * std::max(p->rows, p->cols));
+      p->B16 = take16(p->rows * p->cols);
+    }
+    if (dw16) {
+      p->C16 = take16(p->rows * batch);
+      p->D16 = take16(p->cols * batch);
+    }
+  }
+}
+
+// C (M x N, ldc) = A . B^T on BF16 operands with k contiguous.
+ttc_status gemm16(const uint16_t* A, long lda, const uint16_t* B, long ldb, float* C, long ldc, int M, int N, int K,
+                  hipStream_t s) {
+  static std::atomic<bool> done[kMaxDevices];
+  TTC_HIP(once_per_device(done, [] { return gemm16_set_lds(); }));
+  Gemm16Args g;
+  std::memset(&g, 0, sizeof(g));
+  g.M = M;
+  g.N = N;
+  g.K = K;
+  g.lda = lda;
+  g.ldb = ldb;
+  g.ldc = ldc;
+  g.A = A;
+  g.B = B;
+  g.C = C;
+  g.alpha = 1.f;
+  g.splits = 1;
+  const int tiles = ((M + 255) / 256) * ((N + 255) / 256);
+  g.per_xcd = (tiles % 8 == 0) ? tiles / 8 : 0;
+  TTC_HIP(launch_gemm16(g, s));
+  return TTC_OK;
 }
 
 bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
@@ -407,7 +456,7 @@ ttc_status ttm_apply_dense_query(const ttc_ttm* m, int64_t batch, ttc_prec prec,
     plan_cores(m, (long)batch, backward != 0, a, &p);
   } else {
     LayerPlan p;
-    plan_layer(m, backward != 0, a, &p);
+    plan_layer(m, backward != 0, bf16, (long)batch, a, &p);
   }
   *ws_bytes = a.off;
   return TTC_OK;
@@ -430,8 +479,15 @@ ttc_status ttm_apply_dense(const ttc_ttm* m, const void* d_x, int64_t batch, voi
     return cores_forward(m, p, reinterpret_cast<const float*>(d_x), reinterpret_cast<float*>(d_y), bf16, s);
   }
   LayerPlan p;
-  plan_layer(m, false, a, &p);
+  plan_layer(m, false, bf16, (long)batch, a, &p);
   TTC_TRY(build_dense(m, p, s));
+  const float* X = reinterpret_cast<const float*>(d_x);
+  if (bf16 && use_gemm16(batch, p.rows, p.cols) && aligned16(X)) {
+    TTC_HIP(launch_cvt16(X, p.A16, (long)batch * p.cols, s));
+    TTC_HIP(launch_cvt16(p.Wd, p.B16, p.rows * p.cols, s));
+    return gemm16(p.A16, p.cols, p.B16, p.cols, reinterpret_cast<float*>(d_y), p.rows, (int)batch, (int)p.rows,
+                  (int)p.cols, s);
+  }
   // Y = X . W^T: A = X (batch x cols), B(k = j, n = i) = W[i * cols + j]
   return gemm(true, reinterpret_cast<const float*>(d_x), p.cols, true, p.Wd, p.cols, reinterpret_cast<float*>(d_y),
               p.rows, (int)batch, (int)p.rows, (int)p.cols, bf16, p.slab, s);
@@ -460,19 +516,32 @@ ttc_status ttm_apply_dense_bwd(const ttc_ttm* m, const void* d_x, const void* d_
                           reinterpret_cast<float*>(d_dx), d_dcores, bf16, s);
   }
   LayerPlan p;
-  plan_layer(m, true, a, &p);
+  plan_layer(m, true, bf16, (long)batch, a, &p);
   TTC_TRY(build_dense(m, p, s));
   const float* X = reinterpret_cast<const float*>(d_x);
   const float* dY = reinterpret_cast<const float*>(d_dy);
-  if (d_dx) {
+  const bool al = aligned16(X) && aligned16(dY);
+  if (d_dx && bf16 && al && use_gemm16(batch, p.cols, p.rows)) {
+    // dX = dY . W: A = dY (batch x rows, k = i), B = W^T (cols x rows, k = i)
+    TTC_HIP(launch_cvt16(dY, p.A16, (long)batch * p.rows, s));
+    TTC_HIP(launch_cvt16_t(p.Wd, p.B16, p.rows, p.cols, s));
+    TTC_TRY(gemm16(p.A16, p.rows, p.B16, p.rows, reinterpret_cast<float*>(d_dx), p.cols, (int)batch, (int)p.cols,
+                   (int)p.rows, s));
+  } else if (d_dx) {
     // dX = dY . W: A = dY (batch x rows), B(k = i, n = j) = W[i * cols + j]
     TTC_TRY(gemm(true, dY, p.rows, false, p.Wd, p.cols, reinterpret_cast<float*>(d_dx), p.cols, (int)batch,
                  (int)p.cols, (int)p.rows, bf16, p.slab, s));
   }
   if (!d_dcores) return TTC_OK;
   // dW = dY^T . X into the dense buffer: A(m = i, k = b) = dY[b * rows + i], B(k = b, n = j) = X[b * cols + j]
-  TTC_TRY(gemm(false, dY, p.rows, false, X, p.cols, p.Wd, p.cols, (int)p.rows, (int)p.cols, (int)batch, bf16,
-               p.slab, s));
+  if (bf16 && al && use_gemm16(p.rows, p.cols, batch)) {
+    TTC_HIP(launch_cvt16_t(dY, p.C16, batch, p.rows, s));
+    TTC_HIP(launch_cvt16_t(X, p.D16, batch, p.cols, s));
+    TTC_TRY(gemm16(p.C16, batch, p.D16, batch, p.Wd, p.cols, (int)p.rows, (int)p.cols, (int)batch, s));
+  } else {
+    TTC_TRY(gemm(false, dY, p.rows, false, X, p.cols, p.Wd, p.cols, (int)p.rows, (int)p.cols, (int)batch, bf16,
+                 p.slab, s));
+  }
   // dW -> pair-mode order (the right environment of the last core)
   TTC_TRY(permute_dense(m, 1, p.cols, p.Wd, d == 1 ? reinterpret_cast<float*>(d_dcores[0]) : p.Dp, s));
   const float* Rt = p.Dp;  // Rt_{d-1}: |m_<d-1| x (M_{d-1} R_d)

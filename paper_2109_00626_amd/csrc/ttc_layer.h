@@ -75,6 +75,28 @@ struct TilePermArgs {
 };
 
 hipError_t launch_gemm(bool a_kc, bool b_kc, bool bf16, const GemmArgs& g, hipStream_t s);
+
+// BF16 product C (M x N, FP32, ldc) = alpha * A . B^T for BF16 A (M x K) and
+// B (N x K), both with k contiguous (lda, ldb multiples of 8, 16-byte
+// aligned, K a multiple of 8); 256 x 256 tiles.  per_xcd: tiles per XCD
+// when the tile count is a multiple of 8 (XCD-contiguous tile order), else 0.
+struct Gemm16Args {
+  int M, N, K;
+  long lda, ldb, ldc;
+  const uint16_t* A;
+  const uint16_t* B;
+  float* C;
+  float alpha;
+  int splits;
+  float* slab;
+  int per_xcd;
+};
+hipError_t gemm16_set_lds();
+hipError_t launch_gemm16(const Gemm16Args& g, hipStream_t s);
+// dst = bf16(src), n elements (n a multiple of 8; 16-byte aligned buffers)
+hipError_t launch_cvt16(const float* src, uint16_t* dst, long n, hipStream_t s);
+// dst (cols x rows) = bf16(src (rows x cols))^T
+hipError_t launch_cvt16_t(const float* src, uint16_t* dst, long rows, long cols, hipStream_t s);
 // Elements of the LDS tile of the tiled permutation (at most).
 constexpr int kTilePermElems = 8192;
 hipError_t launch_tile_permute(const TilePermArgs& p, hipStream_t s);

@@ -150,3 +150,25 @@ def test_mse_loss_odd_size(ttc):
     yn, tn = to_np(y), to_np(t)
     assert abs(L.item() - np.mean((yn - tn) ** 2)) <= 1e-12 * np.mean((yn - tn) ** 2)
     assert rel_err(to_np(dy), 2 * (yn - tn) / 1001) <= 1e-6
+
+
+@pytest.mark.parametrize("sched", ["dense"])
+def test_layer_bf16_tile_kernel_ragged(ttc, sched):
+    """The BF16 dense schedule on a shape whose products take the 256 x 256
+    BF16 tile kernel with ragged edges (4000 x 1080 output, 960-long
+    reduction; 4000 x 960 output, 1080-long reduction): forward, dX and
+    every core gradient against the oracle's dense route on the unrounded
+    cores (total error, BF16 bound)."""
+    s = C.TTShape([10, 12, 9], [1, 6, 5, 1], [8, 12, 10])
+    w = C.gen_tt_np(C.SEED_LAYER, 41, s)
+    X = _batch(C.SEED_LAYER, 42, 4000, 960)
+    T = _batch(C.SEED_LAYER, 43, 4000, 1080)
+    wg, _ = to_gpu(w, "f32")
+    Xg, Tg = _upload(X), _upload(T)
+    ref = O.layer_forward_backward(w, to_np(Xg), to_np(Tg))
+    Y = ttc.ttm_apply_dense(wg, Xg, prec="bf16", sched=sched)
+    assert rel_err(to_np(Y), ref["Y"]) <= TOL["bf16"]
+    _, dY = ttc.ttc_mse_loss(Y, Tg)
+    dX, dG = ttc.ttm_apply_dense_bwd(wg, Xg, dY, prec="bf16", sched=sched)
+    assert rel_err(to_np(dX), ref["dX"]) <= TOL["bf16"]
+    assert max_core_rel([to_np(g) for g in dG], ref["dG"]) <= TOL["bf16"]
