@@ -179,9 +179,9 @@ def algorithmic(W):
 # ------------------------------------------------------------- measured peaks
 def measured_peaks(W, stream):
     """Reference rates measured on this GPU beside the nominal peaks: a
-    plain 1 GiB device copy (bytes read + written per second) for HBM, and
-    the vendor FP32 GEMM (torch.mm, hipBLASLt) on the layer's forward shape
-    for FP32 MFMA.  Neither is part of the path; they only give the
+    plain 1 GiB device copy (bytes read + written per second) and a 1 GiB
+    fill (bytes written per second) for HBM, and the vendor FP32 and BF16
+    GEMMs (torch.mm, hipBLASLt) on the layer's forward shape for MFMA.  Neither is part of the path; they only give the
     achieved rates a second scale."""
     import torch
 
@@ -203,6 +203,9 @@ def measured_peaks(W, stream):
     dst = torch.empty_like(src)
     ms = timed(lambda: dst.copy_(src), 10)
     out["hbm_copy_GBs"] = round(2 * 4 * n / (ms * 1e-3) / 1e9, 1)
+    # write-only stream (the natural-form lift and the MPO product are writes)
+    ms = timed(lambda: dst.fill_(0.5), 10)
+    out["hbm_fill_GBs"] = round(4 * n / (ms * 1e-3) / 1e9, 1)
     del src, dst
     if "layer4" in W:
         X = W["layer4"]["X"]
@@ -211,7 +214,10 @@ def measured_peaks(W, stream):
         Wt = torch.randn(4096, 4096, dtype=torch.float32, device="cuda:0", generator=g)
         ms = timed(lambda: torch.mm(X, Wt), 5)
         out["fp32_gemm_TFLOPs"] = round(2.0 * X.shape[0] * 4096 * 4096 / (ms * 1e-3) / 1e12, 2)
-        del Wt
+        Xh, Wh = X.to(torch.bfloat16), Wt.to(torch.bfloat16)
+        ms = timed(lambda: torch.mm(Xh, Wh), 5)
+        out["bf16_gemm_TFLOPs"] = round(2.0 * X.shape[0] * 4096 * 4096 / (ms * 1e-3) / 1e12, 2)
+        del Wt, Xh, Wh
     torch.cuda.synchronize()
     return out
 

@@ -60,13 +60,9 @@ __device__ __forceinline__ Tc lift_value(const LiftCore& c, const Tc* K, int Q, 
   }
 }
 
+// One line (one row bond and mode index: d1 consecutive outputs) of core cc.
 template <typename Tin, typename Tc>
-__global__ __launch_bounds__(256) void lift_kernel(LiftArgs a) {
-  const int L = blockIdx.x;
-  int cc = 0;
-  while (cc + 1 < a.ncores && a.c[cc + 1].line_begin <= L) ++cc;
-  const LiftCore& c = a.c[cc];
-  const int l = L - c.line_begin;
+__device__ __forceinline__ void lift_line(const LiftArgs& a, const LiftCore& c, int l) {
   const int row = l / c.n, i = l - row * c.n;
   const Tc* K = reinterpret_cast<const Tc*>(a.K);
   Tc* dst = reinterpret_cast<Tc*>(c.dst) + (long)l * c.d1;
@@ -103,6 +99,18 @@ __global__ __launch_bounds__(256) void lift_kernel(LiftArgs a) {
   }
 }
 
+// Workgroups walk the lines of every output core in a grid-stride loop (a
+// few thousand workgroups, each writing many lines, rather than one
+// workgroup per line).
+template <typename Tin, typename Tc>
+__global__ __launch_bounds__(256) void lift_kernel(LiftArgs a, int total_lines) {
+  int cc = 0;
+  for (int L = blockIdx.x; L < total_lines; L += gridDim.x) {
+    while (cc + 1 < a.ncores && a.c[cc + 1].line_begin <= L) ++cc;
+    lift_line<Tin, Tc>(a, a.c[cc], L - a.c[cc].line_begin);
+  }
+}
+
 #define TTC_DENSE_MAXR 64
 
 template <typename Tc>
@@ -130,12 +138,16 @@ __global__ __launch_bounds__(256) void dense_kernel(DenseArgs a) {
   reinterpret_cast<Tc*>(a.out)[e] = v[0];
 }
 
+// Workgroups of the lift: eight per compute unit.
+const int kLiftGrid = 2048;
+
 hipError_t launch_lift(ttc_dtype dt, const LiftArgs& a, int total_lines, hipStream_t s) {
   if (total_lines <= 0) return hipSuccess;
+  const int grid = std::min(total_lines, kLiftGrid);
   switch (dt) {
-    case TTC_F64: hipLaunchKernelGGL((lift_kernel<double, double>), dim3(total_lines), dim3(256), 0, s, a); break;
-    case TTC_F32: hipLaunchKernelGGL((lift_kernel<float, float>), dim3(total_lines), dim3(256), 0, s, a); break;
-    default: hipLaunchKernelGGL((lift_kernel<bf16_t, float>), dim3(total_lines), dim3(256), 0, s, a); break;
+    case TTC_F64: hipLaunchKernelGGL((lift_kernel<double, double>), dim3(grid), dim3(256), 0, s, a, total_lines); break;
+    case TTC_F32: hipLaunchKernelGGL((lift_kernel<float, float>), dim3(grid), dim3(256), 0, s, a, total_lines); break;
+    default: hipLaunchKernelGGL((lift_kernel<bf16_t, float>), dim3(grid), dim3(256), 0, s, a, total_lines); break;
   }
   return hipGetLastError();
 }

@@ -37,6 +37,18 @@ __device__ __forceinline__ double wide(T v) {
   return (double)v;
 }
 
+// Rows of length up to 64 x kJacobiChunk are held in registers per pair.
+constexpr int kJacobiChunk = 8;
+
+// The rotation (c, s) that zeroes the off-diagonal entry of the 2 x 2 Gram
+// matrix [[al, ga], [ga, be]] (the smaller of the two equivalent angles).
+__device__ __forceinline__ void jacobi_rotation(double al, double be, double ga, double* c, double* s) {
+  const double zeta = (be - al) / (2.0 * ga);
+  const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  *c = 1.0 / sqrt(1.0 + t * t);
+  *s = *c * t;
+}
+
 }  // namespace
 
 // out[c * m + r] = in[r * n + c] for an m x n row-major matrix, through
@@ -77,6 +89,7 @@ __global__ __launch_bounds__(1024) void svd_jacobi_kernel(T* __restrict__ A, T* 
     const int r = (int)(e / p), c = (int)(e - (long)r * p);
     J[e] = (r == c) ? T(1) : T(0);
   }
+  const bool in_regs = L <= 64 * kJacobiChunk && p <= 64 * kJacobiChunk;
   const int pe = p + (p & 1);  // even count; index p (when p is odd) is a bye
   const int rounds = pe - 1, npairs = pe / 2;
   int sweep = 0, converged = 0;
@@ -94,6 +107,48 @@ __global__ __launch_bounds__(1024) void svd_jacobi_kernel(T* __restrict__ A, T* 
         if (i >= p || j >= p) continue;
         T* ai = A + (long)i * L;
         T* aj = A + (long)j * L;
+        T* ji = J + (long)i * p;
+        T* jj = J + (long)j * p;
+        if (in_regs) {
+          // both rows of A and of J in registers: one load pass (all loads
+          // in flight together) and one store pass per pair
+          double xa[kJacobiChunk], ya[kJacobiChunk], xj[kJacobiChunk], yj[kJacobiChunk];
+#pragma unroll
+          for (int c = 0; c < kJacobiChunk; ++c) {
+            const int t = lane + 64 * c;
+            xa[c] = t < L ? wide(ai[t]) : 0.0;
+            ya[c] = t < L ? wide(aj[t]) : 0.0;
+            xj[c] = t < p ? wide(ji[t]) : 0.0;
+            yj[c] = t < p ? wide(jj[t]) : 0.0;
+          }
+          double al = 0, be = 0, ga = 0;
+#pragma unroll
+          for (int c = 0; c < kJacobiChunk; ++c) {
+            al += xa[c] * xa[c];
+            be += ya[c] * ya[c];
+            ga += xa[c] * ya[c];
+          }
+          al = __shfl(wave_sum(al), 0, 64);
+          be = __shfl(wave_sum(be), 0, 64);
+          ga = __shfl(wave_sum(ga), 0, 64);
+          if (!(fabs(ga) > tol * sqrt(al * be))) continue;
+          double c, s;
+          jacobi_rotation(al, be, ga, &c, &s);
+#pragma unroll
+          for (int q = 0; q < kJacobiChunk; ++q) {
+            const int t = lane + 64 * q;
+            if (t < L) {
+              ai[t] = (T)(c * xa[q] - s * ya[q]);
+              aj[t] = (T)(s * xa[q] + c * ya[q]);
+            }
+            if (t < p) {
+              ji[t] = (T)(c * xj[q] - s * yj[q]);
+              jj[t] = (T)(s * xj[q] + c * yj[q]);
+            }
+          }
+          if (lane == 0) rotated = 1;
+          continue;
+        }
         double al = 0, be = 0, ga = 0;
         for (int t = lane; t < L; t += 64) {
           const double x = wide(ai[t]), y = wide(aj[t]);
@@ -107,17 +162,13 @@ __global__ __launch_bounds__(1024) void svd_jacobi_kernel(T* __restrict__ A, T* 
         be = __shfl(wave_sum(be), 0, 64);
         ga = __shfl(wave_sum(ga), 0, 64);
         if (!(fabs(ga) > tol * sqrt(al * be))) continue;
-        // rotation that zeroes the (i, j) entry of the 2 x 2 Gram matrix
-        const double zeta = (be - al) / (2.0 * ga);
-        const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+        double c, s;
+        jacobi_rotation(al, be, ga, &c, &s);
         for (int q = lane; q < L; q += 64) {
           const double x = wide(ai[q]), y = wide(aj[q]);
           ai[q] = (T)(c * x - s * y);
           aj[q] = (T)(s * x + c * y);
         }
-        T* ji = J + (long)i * p;
-        T* jj = J + (long)j * p;
         for (int q = lane; q < p; q += 64) {
           const double x = wide(ji[q]), y = wide(jj[q]);
           ji[q] = (T)(c * x - s * y);

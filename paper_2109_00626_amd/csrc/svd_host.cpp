@@ -7,6 +7,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 #include <string>
@@ -56,6 +58,22 @@ struct SvdPlan {
 };
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Rotation threshold of the Jacobi SVD: a pair counts as orthogonal when
+// |a_i . a_j| <= L u ||a_i|| ||a_j|| for vectors of length L in a storage
+// precision of unit roundoff u (the rounding level such dot products reach;
+// a tighter threshold keeps rotating pairs whose overlap is rounding noise).
+double jacobi_tol(double unit, int L) { return unit * std::max(L, 16); }
+
+// With TTC_SVD_TRACE set, one line per SVD on stderr: sweeps run and
+// whether the last sweep rotated nothing (reads the kernel's info words).
+void trace_sweeps(const char* who, int k, int p, int L, const int* info_d) {
+  static const bool on = std::getenv("TTC_SVD_TRACE") != nullptr;
+  if (!on) return;
+  int info[2] = {0, 0};
+  if (hipMemcpy(info, info_d, sizeof(info), hipMemcpyDeviceToHost) != hipSuccess) return;
+  std::fprintf(stderr, "%s split %d: p %d L %d sweeps %d converged %d\n", who, k, p, L, info[0], info[1]);
+}
 
 ttc_status plan_svd(int32_t order, const int32_t* dims, ttc_dtype dtype, int32_t max_rank, SvdPlan* P) {
   if (order < 1 || order > TTC_MAX_ORDER) return fail(TTC_ERR_SHAPE, "tt_svd: order outside [1, 32]");
@@ -161,10 +179,11 @@ ttc_status tt_svd(const void* d_x, int32_t order, const int32_t* dims, ttc_dtype
       SVD_HIP(launch_svd_transpose(dtype, cur, tbuf, (int)m, (int)n, s));
       A = tbuf;
     }
-    SVD_HIP(launch_svd_jacobi(dtype, A, J, sigma, info_d, p, L, kMaxSweeps, 2.0 * unit * std::sqrt((double)L), s));
+    SVD_HIP(launch_svd_jacobi(dtype, A, J, sigma, info_d, p, L, kMaxSweeps, jacobi_tol(unit, L), s));
     sg.assign(p, 0.0);
     SVD_HIP(hipMemcpyAsync(sg.data(), sigma, sizeof(double) * p, hipMemcpyDeviceToHost, s));
     SVD_HIP(hipStreamSynchronize(s));
+    trace_sweeps("tt_svd", k, p, L, info_d);
     if (k == 0) {
       // ||X||_F from the first unfolding's singular values
       double nx2 = 0;
@@ -286,11 +305,11 @@ ttc_status svd_of(ttc_dtype dt, void* M, long m, long n, char* ws, const RoundPl
     *A = ws + P.off_t;
   }
   SVD_HIP(launch_svd_jacobi(dt, *A, ws + P.off_j, reinterpret_cast<double*>(ws + P.off_sigma),
-                            reinterpret_cast<int*>(ws + P.off_info), p, L, kMaxSweeps,
-                            2.0 * unit * std::sqrt((double)L), s));
+                            reinterpret_cast<int*>(ws + P.off_info), p, L, kMaxSweeps, jacobi_tol(unit, L), s));
   sg.assign(p, 0.0);
   SVD_HIP(hipMemcpyAsync(sg.data(), ws + P.off_sigma, sizeof(double) * p, hipMemcpyDeviceToHost, s));
   SVD_HIP(hipStreamSynchronize(s));
+  trace_sweeps("tt_round", 0, p, L, reinterpret_cast<int*>(ws + P.off_info));
   order.resize(p);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return sg[a] > sg[b]; });

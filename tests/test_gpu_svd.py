@@ -103,7 +103,8 @@ def test_svd_rank_one_and_zero(ttc):
 def test_svd_fp32(ttc):
     """FP32 tensor, FP32 storage with FP64 dot products: ranks equal the
     oracle's (on the FP32 values), reconstruction within the FP32 bound,
-    left cores orthonormal."""
+    left cores orthonormal to the Jacobi threshold (pairs stop rotating at
+    |a_i . a_j| <= L u ||a_i|| ||a_j||, about 3e-5 for L = 480 in FP32)."""
     X = _dense(5, (12, 10, 8, 6))
     xg, Xs = _upload(X, "f32")
     cores = [to_np(c) for c in ttc.tt_svd(xg)]
@@ -112,7 +113,7 @@ def test_svd_fp32(ttc):
     assert rel_err(O.tt_full(cores), Xs) <= TOL["f32"]
     for G in cores[:-1]:
         U = G.reshape(-1, G.shape[2])
-        assert np.max(np.abs(U.T @ U - np.eye(U.shape[1]))) <= 1e-5
+        assert np.max(np.abs(U.T @ U - np.eye(U.shape[1]))) <= 1e-4
 
 
 def test_svd_max_rank_caps(ttc):
