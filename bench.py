@@ -45,6 +45,8 @@ def parse():
                     help="skip the measurements beside the step (BF16 batch, plain loop, BF16 layer, measured peaks)")
     ap.add_argument("--batch-dtype", default="f32", choices=["f32", "bf16"],
                     help="core dtype of the batch part (bf16: the BF16 schedule as the timed part, for profiling it)")
+    ap.add_argument("--layer-dtype", default="f32", choices=["f32", "bf16"],
+                    help="arithmetic of the layer part (bf16: the BF16-MFMA option as the timed part, for profiling it)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB mebibytes five times (counter calibration)")
     return ap.parse_args()
@@ -407,7 +409,7 @@ def main():
     stream = torch.cuda.current_stream()
     for _ in range(args.warmup):
         for p in parts:
-            run_part(p, W, ttc)
+            run_part(p, W, ttc, args.layer_dtype)
     torch.cuda.synchronize()
     ev = {p: [] for p in parts}
     t0 = time.perf_counter()
@@ -416,7 +418,7 @@ def main():
             a = torch.cuda.Event(enable_timing=True)
             b = torch.cuda.Event(enable_timing=True)
             a.record(stream)
-            run_part(p, W, ttc)
+            run_part(p, W, ttc, args.layer_dtype)
             b.record(stream)
             ev[p].append((a, b))
     torch.cuda.synchronize()
@@ -435,7 +437,7 @@ def main():
             a = torch.cuda.Event(enable_timing=True)
             b = torch.cuda.Event(enable_timing=True)
             a.record(stream)
-            ttc.ttm_apply_dense(d["w"], d["X"])
+            ttc.ttm_apply_dense(d["w"], d["X"], prec=args.layer_dtype)
             b.record(stream)
             evs.append((a, b))
         torch.cuda.synchronize()
@@ -450,7 +452,14 @@ def main():
         parts_out[p] = o
     dominant = max(parts, key=lambda p: part_ms[p])
     # roofline of the dominant part's main kernel
-    if dominant == "layer4":
+    if dominant == "layer4" and args.layer_dtype == "bf16":
+        ach = alg["layer4"]["fwd_flops"] / (fwd_ms * 1e-3) / 1e12
+        roof = {"bound": "mfma", "kernel": "gemm16_kernel (BF16 16x16x32 MFMA), measured as the whole forward call "
+                                            "(W rebuild, operand conversions, product)",
+                "achieved": round(ach, 2), "peak": PEAK["bf16_TFLOPs"], "unit": "TFLOP/s",
+                "frac": round(ach / PEAK["bf16_TFLOPs"], 4), "traffic": recorded_traffic("gemm16_kernel"),
+                "per_launch": "2 * 8192 * 4096 * 4096 FLOP (+ 1.1 GFLOP core chain)"}
+    elif dominant == "layer4":
         gemm_ms = fwd_ms
         ach = alg["layer4"]["fwd_flops"] / (gemm_ms * 1e-3) / 1e12
         roof = {"bound": "mfma", "kernel": "gemm_kernel (FP32 16x16x4 MFMA), measured as the whole forward call",

@@ -10,8 +10,10 @@
 // Tiling: a 512-thread workgroup (8 waves, 4 x 2) computes a 256 x 256 tile,
 // each wave 64 x 128 as 4 x 8 tiles of 16 x 16 (128 FP32 accumulators per
 // lane).  k advances 64 at a time through two LDS buffers (each operand tile
-// 256 rows x 64 k, rows padded to 72 elements so the 16 lanes of a fragment
-// read hit distinct banks): the next k-slice's global loads (four 16-byte
+// 256 rows x 64 k, 128-byte rows whose eight 16-byte chunks are stored in
+// the order chunk ^ ((row / 2) % 8), so that the 16 lanes of a fragment read
+// (16 rows, one chunk) and of a staging write (two rows, eight chunks each)
+// fall on distinct banks): the next k-slice's global loads (four 16-byte
 // loads per operand per thread) are issued before the current slice's MFMAs
 // and stored to the other buffer after them.  Workgroups are dealt to the
 // XCDs round-robin; the tile index is remapped so that each XCD walks a
@@ -26,7 +28,7 @@ namespace ttc {
 #define G16_BM 256
 #define G16_BN 256
 #define G16_BK 64
-#define G16_P (G16_BK + 8)
+#define G16_P G16_BK
 #define G16_THREADS 512
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
@@ -67,7 +69,7 @@ __device__ __forceinline__ void g16_store(uint16_t* S, const u32x4* r) {
   for (int q = 0; q < 4; ++q) {
     const int c = threadIdx.x + G16_THREADS * q;
     const int row = c >> 3, kc = (c & 7) * 8;
-    *reinterpret_cast<u32x4*>(S + row * G16_P + kc) = r[q];
+    *reinterpret_cast<u32x4*>(S + row * G16_P + ((kc >> 3) ^ ((row >> 1) & 7)) * 8) = r[q];
   }
 }
 
@@ -110,15 +112,18 @@ __global__ __launch_bounds__(G16_THREADS) void gemm16_kernel(Gemm16Args g) {
       g16_load(g.A, g.lda, m0, g.M, k0, kend, ra);
       g16_load(g.B, g.ldb, n0, g.N, k0, kend, rb);
     }
-    const uint16_t* a_s = As + buf * G16_BM * G16_P + (wm * 64 + li) * G16_P + 8 * lg;
-    const uint16_t* b_s = Bs + buf * G16_BN * G16_P + (wn * 128 + li) * G16_P + 8 * lg;
+    // rows wm*64 + 16i + li (resp. wn*128 + 16j + li) have (row / 2) % 8 = li / 2
+    const int swz = (li >> 1) & 7;
+    const uint16_t* a_s = As + buf * G16_BM * G16_P + (wm * 64 + li) * G16_P;
+    const uint16_t* b_s = Bs + buf * G16_BN * G16_P + (wn * 128 + li) * G16_P;
 #pragma unroll
     for (int kk = 0; kk < G16_BK; kk += 32) {
+      const int ch = (((kk >> 3) + lg) ^ swz) * 8;
       bf16x8 av[4], bv[8];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) av[i] = *reinterpret_cast<const bf16x8*>(a_s + 16 * i * G16_P + kk);
+      for (int i = 0; i < 4; ++i) av[i] = *reinterpret_cast<const bf16x8*>(a_s + 16 * i * G16_P + ch);
 #pragma unroll
-      for (int j = 0; j < 8; ++j) bv[j] = *reinterpret_cast<const bf16x8*>(b_s + 16 * j * G16_P + kk);
+      for (int j = 0; j < 8; ++j) bv[j] = *reinterpret_cast<const bf16x8*>(b_s + 16 * j * G16_P + ch);
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll

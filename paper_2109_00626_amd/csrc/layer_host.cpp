@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -80,8 +81,14 @@ struct LayerPlan {
 
 // A product goes to the BF16 tile kernel when its reduction length is a
 // multiple of 8 and it has enough 256 x 256 tiles to fill the GPU.
+// TTC_GEMM16=0 keeps every BF16 product on the 128 x 128-tile kernel (for
+// timing the two against each other).
 bool use_gemm16(long M, long N, long K) {
-  return K % 8 == 0 && ((M + 255) / 256) * ((N + 255) / 256) >= 64;
+  static const bool off = [] {
+    const char* e = std::getenv("TTC_GEMM16");
+    return e && e[0] == '0';
+  }();
+  return !off && K % 8 == 0 && ((M + 255) / 256) * ((N + 255) / 256) >= 64;
 }
 
 void plan_layer(const ttc_ttm* m, bool backward, bool bf16, long batch, Arena& a, LayerPlan* p) {
