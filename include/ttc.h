@@ -314,8 +314,10 @@ ttc_status tt_contract_pairs(const ttc_tt* x, const ttc_tt* y, const int32_t* xm
  * tt_svd: ranks (host, N+1) receives the ranks; core k is written row-major
  *   (R_k, I_k, R_{k+1}) at the start of d_cores[k] (device, caller-owned,
  *   sized from rank_cap).  The ranks depend on the singular values, so the
- *   call synchronises `stream` once per split (N-1 times) and returns with
- *   the last copy queued.  X is not modified.
+ *   call synchronises `stream` once per split (N-1 times; once per Jacobi
+ *   sweep for an unfolding with more than 32 rows and columns, whose rounds
+ *   run as one launch each) and returns with the last copy queued.  X is
+ *   not modified.
  * ------------------------------------------------------------------------ */
 ttc_status tt_svd_query(int32_t order, const int32_t* dims, ttc_dtype dtype, int32_t max_rank,
                         int32_t* rank_cap, size_t* ws_bytes);
@@ -337,7 +339,7 @@ ttc_status tt_svd(const void* d_x, int32_t order, const int32_t* dims, ttc_dtype
  * side of the widest core unfolding, at most 4096).  tt_round: ranks (host,
  * N+1) receives the ranks, core k is written (R_k, I_k, R_{k+1}) at the start
  * of d_cores[k]; the input cores are not modified.  Synchronises `stream`
- * once per split (2N - 2 times).
+ * once per split (2N - 2 times), or once per Jacobi sweep as in tt_svd.
  * ------------------------------------------------------------------------ */
 ttc_status tt_round_query(const ttc_tt* x, int32_t max_rank, int32_t* rank_cap, size_t* ws_bytes);
 ttc_status tt_round(const ttc_tt* x, double eps, int32_t max_rank, int32_t* ranks, void* const* d_cores,

@@ -390,15 +390,33 @@ __global__ __launch_bounds__(256) void tile_permute_kernel(TilePermArgs p) {
   }
 }
 
-// dst[m * N + n] = src[map(m, n)], one thread per destination element.
-__global__ __launch_bounds__(256) void gather_mapped_kernel(GatherArgs a) {
-  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= a.M * a.N) return;
-  const long m = e / a.N, n = e - m * a.N;
-  const long q = m % a.map.mr0, t = m / a.map.mr0;
-  const long src = (t / a.map.mr1) * a.map.ms2 + (t % a.map.mr1) * a.map.ms1 + q * a.map.ms0 +
-                   (n / a.map.nr0) * a.map.ns1 + (n % a.map.nr0) * a.map.ns0;
-  a.dst[e] = a.src[src];
+// dst[m * N + n] = src[map(m, n)]: one wave per destination row (rows
+// grid-stride), the row's part of the map computed once per row in scalar
+// registers; along the row the map is n -> (n / nr0) ns1 + (n % nr0) ns0,
+// runs of nr0 consecutive elements when ns0 = 1.  vec: ns0 = 1, nr0, N and
+// every row offset multiples of 4 (four elements per lane, 16-byte loads and
+// stores).
+__global__ __launch_bounds__(256) void gather_mapped_kernel(GatherArgs a, int vec) {
+  const int lane = threadIdx.x & 63;
+  const long waves = (long)gridDim.x * 4;
+  const int nr0 = a.map.nr0, N = (int)a.N;
+  for (long m = (long)blockIdx.x * 4 + (threadIdx.x >> 6); m < a.M; m += waves) {
+    const long q = m % a.map.mr0, t = m / a.map.mr0;
+    const long base = (t / a.map.mr1) * a.map.ms2 + (t % a.map.mr1) * a.map.ms1 + q * a.map.ms0;
+    float* drow = a.dst + m * a.N;
+    if (vec) {
+      for (int n = 4 * lane; n < N; n += 256) {
+        const int hi = n / nr0;
+        const f32x4 v = *reinterpret_cast<const f32x4*>(a.src + base + (long)hi * a.map.ns1 + (n - hi * nr0));
+        *reinterpret_cast<f32x4*>(drow + n) = v;
+      }
+    } else {
+      for (int n = lane; n < N; n += 64) {
+        const int hi = n / nr0;
+        drow[n] = a.src[base + (long)hi * a.map.ns1 + (long)(n - hi * nr0) * a.map.ns0];
+      }
+    }
+  }
 }
 
 // Core G[r, i, j, r1] (R x I x J x R1) <-> Wp[(j, r), (i, r1)], one thread
@@ -509,9 +527,12 @@ hipError_t launch_gemm(bool a_kc, bool b_kc, bool bf16, const GemmArgs& g, hipSt
 }
 
 hipError_t launch_gather(const GatherArgs& a, hipStream_t s) {
-  const long n = a.M * a.N;
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(gather_mapped_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a);
+  if (a.M <= 0 || a.N <= 0) return hipSuccess;
+  const IdxMap& mp = a.map;
+  const bool vec = mp.ns0 == 1 && mp.nr0 % 4 == 0 && a.N % 4 == 0 && mp.ns1 % 4 == 0 && mp.ms0 % 4 == 0 &&
+                   mp.ms1 % 4 == 0 && mp.ms2 % 4 == 0 && ((uintptr_t)a.src & 15) == 0 && ((uintptr_t)a.dst & 15) == 0;
+  const long blocks = std::min<long>((a.M + 3) / 4, 16384);
+  hipLaunchKernelGGL(gather_mapped_kernel, dim3((unsigned)blocks), dim3(256), 0, s, a, vec ? 1 : 0);
   return hipGetLastError();
 }
 

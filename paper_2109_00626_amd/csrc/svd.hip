@@ -202,6 +202,86 @@ __global__ __launch_bounds__(1024) void svd_jacobi_kernel(T* __restrict__ A, T* 
   }
 }
 
+// One round of the same iteration spread over the GPU, for many vectors: a
+// workgroup per pair of round `rd` (circle order as above), FP64 dot products
+// reduced over the workgroup, the rotation applied to both rows of A and of
+// J.  *rotated is set when a pair was rotated.  Consecutive rounds are
+// consecutive launches (each round's pairs are disjoint, and the next round
+// starts after this one ends).
+template <typename T>
+__global__ __launch_bounds__(256) void svd_round_kernel(T* __restrict__ A, T* __restrict__ J, int p, int L, int rd,
+                                                        double tol, int* rotated) {
+  __shared__ double red[3][4];
+  const int pe = p + (p & 1);
+  const int k = blockIdx.x;
+  const int s1 = k, s2 = pe - 1 - k;
+  const int i = s1 == 0 ? 0 : 1 + (s1 - 1 + rd) % (pe - 1);
+  const int j = 1 + (s2 - 1 + rd) % (pe - 1);
+  if (i >= p || j >= p) return;  // the bye: uniform over the workgroup
+  T* ai = A + (long)i * L;
+  T* aj = A + (long)j * L;
+  double al = 0, be = 0, ga = 0;
+  for (int t = threadIdx.x; t < L; t += blockDim.x) {
+    const double x = wide(ai[t]), y = wide(aj[t]);
+    al += x * x;
+    be += y * y;
+    ga += x * y;
+  }
+  al = wave_sum(al);
+  be = wave_sum(be);
+  ga = wave_sum(ga);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    red[0][wave] = al;
+    red[1][wave] = be;
+    red[2][wave] = ga;
+  }
+  __syncthreads();
+  al = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+  be = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+  ga = red[2][0] + red[2][1] + red[2][2] + red[2][3];
+  if (!(fabs(ga) > tol * sqrt(al * be))) return;  // uniform: every thread read the same sums
+  double c, s;
+  jacobi_rotation(al, be, ga, &c, &s);
+  for (int q = threadIdx.x; q < L; q += blockDim.x) {
+    const double x = wide(ai[q]), y = wide(aj[q]);
+    ai[q] = (T)(c * x - s * y);
+    aj[q] = (T)(s * x + c * y);
+  }
+  T* ji = J + (long)i * p;
+  T* jj = J + (long)j * p;
+  for (int q = threadIdx.x; q < p; q += blockDim.x) {
+    const double x = wide(ji[q]), y = wide(jj[q]);
+    ji[q] = (T)(c * x - s * y);
+    jj[q] = (T)(s * x + c * y);
+  }
+  if (threadIdx.x == 0) *rotated = 1;
+}
+
+// J = identity (p x p) and sigma[i] = ||A[i, :]|| (FP64), one wave per row.
+template <typename T>
+__global__ __launch_bounds__(256) void svd_ident_kernel(T* __restrict__ J, int p) {
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < (long)p * p; e += (long)gridDim.x * blockDim.x) {
+    const int r = (int)(e / p), c = (int)(e - (long)r * p);
+    J[e] = (r == c) ? T(1) : T(0);
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void svd_norms_kernel(const T* __restrict__ A, double* sigma, int p, int L) {
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= p) return;
+  const T* a = A + (long)row * L;
+  double s = 0;
+  for (int t = lane; t < L; t += 64) {
+    const double x = wide(a[t]);
+    s += x * x;
+  }
+  s = wave_sum(s);
+  if (lane == 0) sigma[row] = sqrt(s);
+}
+
 // Core k and the next running matrix from the converged Jacobi state, for
 // the r selected singular values sel[0..r) (in decreasing order):
 //   G[row, c] (m x r): wide case J[sel_c, row]; tall case A[sel_c, row] / sigma_c;
@@ -250,6 +330,36 @@ hipError_t launch_svd_jacobi(ttc_dtype dt, void* A, void* J, double* sigma, int*
   else
     hipLaunchKernelGGL(svd_jacobi_kernel<float>, dim3(1), dim3(1024), 0, s, (float*)A, (float*)J, sigma, info, p, L,
                        max_sweeps, tol);
+  return hipGetLastError();
+}
+
+hipError_t launch_svd_round(ttc_dtype dt, void* A, void* J, int p, int L, int rd, double tol, int* rotated,
+                            hipStream_t s) {
+  const int npairs = (p + (p & 1)) / 2;
+  if (dt == TTC_F64)
+    hipLaunchKernelGGL(svd_round_kernel<double>, dim3(npairs), dim3(256), 0, s, (double*)A, (double*)J, p, L, rd,
+                       tol, rotated);
+  else
+    hipLaunchKernelGGL(svd_round_kernel<float>, dim3(npairs), dim3(256), 0, s, (float*)A, (float*)J, p, L, rd, tol,
+                       rotated);
+  return hipGetLastError();
+}
+
+hipError_t launch_svd_ident(ttc_dtype dt, void* J, int p, hipStream_t s) {
+  const int blocks = (int)std::min<long>(((long)p * p + 255) / 256, 4096);
+  if (dt == TTC_F64)
+    hipLaunchKernelGGL(svd_ident_kernel<double>, dim3(blocks), dim3(256), 0, s, (double*)J, p);
+  else
+    hipLaunchKernelGGL(svd_ident_kernel<float>, dim3(blocks), dim3(256), 0, s, (float*)J, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_svd_norms(ttc_dtype dt, const void* A, double* sigma, int p, int L, hipStream_t s) {
+  const int blocks = (p + 3) / 4;
+  if (dt == TTC_F64)
+    hipLaunchKernelGGL(svd_norms_kernel<double>, dim3(blocks), dim3(256), 0, s, (const double*)A, sigma, p, L);
+  else
+    hipLaunchKernelGGL(svd_norms_kernel<float>, dim3(blocks), dim3(256), 0, s, (const float*)A, sigma, p, L);
   return hipGetLastError();
 }
 

@@ -23,6 +23,10 @@ hipError_t launch_svd_jacobi(ttc_dtype dt, void* A, void* J, double* sigma, int*
                              int max_sweeps, double tol, hipStream_t s);
 hipError_t launch_svd_split(ttc_dtype dt, const void* A, const void* J, const double* sigma, const int* sel,
                             int tall, int m, int n, int p, int r, void* G, void* C, hipStream_t s);
+hipError_t launch_svd_round(ttc_dtype dt, void* A, void* J, int p, int L, int rd, double tol, int* rotated,
+                            hipStream_t s);
+hipError_t launch_svd_ident(ttc_dtype dt, void* J, int p, hipStream_t s);
+hipError_t launch_svd_norms(ttc_dtype dt, const void* A, double* sigma, int p, int L, hipStream_t s);
 hipError_t launch_svd_rsplit(ttc_dtype dt, const void* A, const void* J, const double* sigma, const int* sel,
                              int tall, int m, int n, int p, int r, void* Q, void* B, hipStream_t s);
 hipError_t launch_svd_small_gemm(ttc_dtype dt, const void* A, const void* B, void* C, long m, int K, long n,
@@ -66,13 +70,54 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 double jacobi_tol(double unit, int L) { return unit * std::max(L, 16); }
 
 // With TTC_SVD_TRACE set, one line per SVD on stderr: sweeps run and
-// whether the last sweep rotated nothing (reads the kernel's info words).
-void trace_sweeps(const char* who, int k, int p, int L, const int* info_d) {
+// whether the last sweep rotated nothing.
+void trace_sweeps(const char* who, int k, int p, int L, int sweeps, int converged) {
   static const bool on = std::getenv("TTC_SVD_TRACE") != nullptr;
-  if (!on) return;
-  int info[2] = {0, 0};
-  if (hipMemcpy(info, info_d, sizeof(info), hipMemcpyDeviceToHost) != hipSuccess) return;
-  std::fprintf(stderr, "%s split %d: p %d L %d sweeps %d converged %d\n", who, k, p, L, info[0], info[1]);
+  if (on) std::fprintf(stderr, "%s split %d: p %d L %d sweeps %d converged %d\n", who, k, p, L, sweeps, converged);
+}
+
+// Up to this many vectors one workgroup runs the whole Jacobi iteration
+// (its rounds are short); above it each round is a launch with one
+// workgroup per pair, so the p / 2 pairs of a round run on as many CUs.
+const int kOneWorkgroupVectors = 32;
+
+// Jacobi SVD of the p rows (length L) of A: rotations accumulated in J
+// (p x p), row norms (the singular values) into sigma and then into sg on the
+// host, in row order.  flag_d: two device ints of scratch.  Synchronises the
+// stream at the end (and once per sweep on the many-workgroup path).
+ttc_status jacobi_svd(ttc_dtype dt, void* A, void* J, double* sigma, int* flag_d, int p, int L, double tol,
+                      hipStream_t s, std::vector<double>& sg, const char* who, int k) {
+  int sweeps = 0, converged = 0;
+  sg.assign(p, 0.0);
+  if (p <= kOneWorkgroupVectors) {
+    SVD_HIP(launch_svd_jacobi(dt, A, J, sigma, flag_d, p, L, kMaxSweeps, tol, s));
+    int info[2] = {0, 0};
+    SVD_HIP(hipMemcpyAsync(info, flag_d, sizeof(info), hipMemcpyDeviceToHost, s));
+    SVD_HIP(hipMemcpyAsync(sg.data(), sigma, sizeof(double) * p, hipMemcpyDeviceToHost, s));
+    SVD_HIP(hipStreamSynchronize(s));
+    sweeps = info[0];
+    converged = info[1];
+  } else {
+    SVD_HIP(launch_svd_ident(dt, J, p, s));
+    const int rounds = p + (p & 1) - 1;
+    while (sweeps < kMaxSweeps) {
+      SVD_HIP(hipMemsetAsync(flag_d, 0, sizeof(int), s));
+      for (int rd = 0; rd < rounds; ++rd) SVD_HIP(launch_svd_round(dt, A, J, p, L, rd, tol, flag_d, s));
+      int flag = 0;
+      SVD_HIP(hipMemcpyAsync(&flag, flag_d, sizeof(int), hipMemcpyDeviceToHost, s));
+      SVD_HIP(hipStreamSynchronize(s));
+      ++sweeps;
+      if (!flag) {
+        converged = 1;
+        break;
+      }
+    }
+    SVD_HIP(launch_svd_norms(dt, A, sigma, p, L, s));
+    SVD_HIP(hipMemcpyAsync(sg.data(), sigma, sizeof(double) * p, hipMemcpyDeviceToHost, s));
+    SVD_HIP(hipStreamSynchronize(s));
+  }
+  trace_sweeps(who, k, p, L, sweeps, converged);
+  return TTC_OK;
 }
 
 ttc_status plan_svd(int32_t order, const int32_t* dims, ttc_dtype dtype, int32_t max_rank, SvdPlan* P) {
@@ -179,11 +224,7 @@ ttc_status tt_svd(const void* d_x, int32_t order, const int32_t* dims, ttc_dtype
       SVD_HIP(launch_svd_transpose(dtype, cur, tbuf, (int)m, (int)n, s));
       A = tbuf;
     }
-    SVD_HIP(launch_svd_jacobi(dtype, A, J, sigma, info_d, p, L, kMaxSweeps, jacobi_tol(unit, L), s));
-    sg.assign(p, 0.0);
-    SVD_HIP(hipMemcpyAsync(sg.data(), sigma, sizeof(double) * p, hipMemcpyDeviceToHost, s));
-    SVD_HIP(hipStreamSynchronize(s));
-    trace_sweeps("tt_svd", k, p, L, info_d);
+    SVD_TRY(jacobi_svd(dtype, A, J, sigma, info_d, p, L, jacobi_tol(unit, L), s, sg, "tt_svd", k));
     if (k == 0) {
       // ||X||_F from the first unfolding's singular values
       double nx2 = 0;
@@ -304,12 +345,8 @@ ttc_status svd_of(ttc_dtype dt, void* M, long m, long n, char* ws, const RoundPl
     SVD_HIP(launch_svd_transpose(dt, M, ws + P.off_t, (int)m, (int)n, s));
     *A = ws + P.off_t;
   }
-  SVD_HIP(launch_svd_jacobi(dt, *A, ws + P.off_j, reinterpret_cast<double*>(ws + P.off_sigma),
-                            reinterpret_cast<int*>(ws + P.off_info), p, L, kMaxSweeps, jacobi_tol(unit, L), s));
-  sg.assign(p, 0.0);
-  SVD_HIP(hipMemcpyAsync(sg.data(), ws + P.off_sigma, sizeof(double) * p, hipMemcpyDeviceToHost, s));
-  SVD_HIP(hipStreamSynchronize(s));
-  trace_sweeps("tt_round", 0, p, L, reinterpret_cast<int*>(ws + P.off_info));
+  SVD_TRY(jacobi_svd(dt, *A, ws + P.off_j, reinterpret_cast<double*>(ws + P.off_sigma),
+                     reinterpret_cast<int*>(ws + P.off_info), p, L, jacobi_tol(unit, L), s, sg, "tt_round", 0));
   order.resize(p);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return sg[a] > sg[b]; });
