@@ -188,6 +188,36 @@ __global__ __launch_bounds__(256) void cvt16_t_kernel(const float* __restrict__ 
   }
 }
 
+// Both copies of one source in one pass: dst (rows x cols) = bf16(src) and
+// dst_t (cols x rows) = bf16(src)^T.
+__global__ __launch_bounds__(256) void cvt16_both_kernel(const float* __restrict__ src, uint16_t* __restrict__ dst,
+                                                         uint16_t* __restrict__ dst_t, long rows, long cols) {
+  __shared__ float tile[64][65];
+  const long r0 = (long)blockIdx.x * 64, c0 = (long)blockIdx.y * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // 64 x 4
+#pragma unroll 4
+  for (int q = 0; q < 64; q += 4) {
+    const long r = r0 + ty + q, c = c0 + tx;
+    const bool in = r < rows && c < cols;
+    const float v = in ? src[r * cols + c] : 0.f;
+    tile[ty + q][tx] = v;
+    if (in) dst[r * cols + c] = f32_to_bf16(v);
+  }
+  __syncthreads();
+#pragma unroll 4
+  for (int q = 0; q < 64; q += 4) {
+    const long c = c0 + ty + q, r = r0 + tx;
+    if (r < rows && c < cols) dst_t[c * rows + r] = f32_to_bf16(tile[tx][ty + q]);
+  }
+}
+
+hipError_t launch_cvt16_both(const float* src, uint16_t* dst, uint16_t* dst_t, long rows, long cols, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((rows + 63) / 64), (unsigned)((cols + 63) / 64));
+  hipLaunchKernelGGL(cvt16_both_kernel, grid, dim3(256), 0, s, src, dst, dst_t, rows, cols);
+  return hipGetLastError();
+}
+
 hipError_t gemm16_set_lds() {
   return hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm16_kernel),
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)gemm16_lds_bytes());

@@ -528,9 +528,16 @@ ttc_status ttm_apply_dense_bwd(const ttc_ttm* m, const void* d_x, const void* d_
   const float* X = reinterpret_cast<const float*>(d_x);
   const float* dY = reinterpret_cast<const float*>(d_dy);
   const bool al = aligned16(X) && aligned16(dY);
-  if (d_dx && bf16 && al && use_gemm16(batch, p.cols, p.rows)) {
-    // dX = dY . W: A = dY (batch x rows, k = i), B = W^T (cols x rows, k = i)
+  const bool dx16 = d_dx && bf16 && al && use_gemm16(batch, p.cols, p.rows);
+  const bool dw16 = d_dcores && bf16 && al && use_gemm16(p.rows, p.cols, batch);
+  if (dx16 && dw16) {
+    // dY in both layouts from one read
+    TTC_HIP(launch_cvt16_both(dY, p.A16, p.C16, batch, p.rows, s));
+  } else if (dx16) {
     TTC_HIP(launch_cvt16(dY, p.A16, (long)batch * p.rows, s));
+  }
+  if (dx16) {
+    // dX = dY . W: A = dY (batch x rows, k = i), B = W^T (cols x rows, k = i)
     TTC_HIP(launch_cvt16_t(p.Wd, p.B16, p.rows, p.cols, s));
     TTC_TRY(gemm16(p.A16, p.rows, p.B16, p.rows, reinterpret_cast<float*>(d_dx), p.cols, (int)batch, (int)p.cols,
                    (int)p.rows, s));
@@ -541,8 +548,8 @@ ttc_status ttm_apply_dense_bwd(const ttc_ttm* m, const void* d_x, const void* d_
   }
   if (!d_dcores) return TTC_OK;
   // dW = dY^T . X into the dense buffer: A(m = i, k = b) = dY[b * rows + i], B(k = b, n = j) = X[b * cols + j]
-  if (bf16 && al && use_gemm16(p.rows, p.cols, batch)) {
-    TTC_HIP(launch_cvt16_t(dY, p.C16, batch, p.rows, s));
+  if (dw16) {
+    if (!dx16) TTC_HIP(launch_cvt16_t(dY, p.C16, batch, p.rows, s));
     TTC_HIP(launch_cvt16_t(X, p.D16, batch, p.cols, s));
     TTC_TRY(gemm16(p.C16, batch, p.D16, batch, p.Wd, p.cols, (int)p.rows, (int)p.cols, (int)batch, s));
   } else {

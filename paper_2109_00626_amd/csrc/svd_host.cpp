@@ -64,10 +64,11 @@ struct SvdPlan {
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 // Rotation threshold of the Jacobi SVD: a pair counts as orthogonal when
-// |a_i . a_j| <= L u ||a_i|| ||a_j|| for vectors of length L in a storage
-// precision of unit roundoff u (the rounding level such dot products reach;
-// a tighter threshold keeps rotating pairs whose overlap is rounding noise).
-double jacobi_tol(double unit, int L) { return unit * std::max(L, 16); }
+// |a_i . a_j| <= 32 u sqrt(L) ||a_i|| ||a_j|| for vectors of length L stored
+// with unit roundoff u, a margin over the rounding level such normalised
+// dot products reach (a tighter threshold keeps rotating pairs whose
+// overlap is rounding noise).
+double jacobi_tol(double unit, int L) { return 32.0 * unit * std::sqrt((double)std::max(L, 4)); }
 
 // With TTC_SVD_TRACE set, one line per SVD on stderr: sweeps run and
 // whether the last sweep rotated nothing.

@@ -97,6 +97,8 @@ hipError_t launch_gemm16(const Gemm16Args& g, hipStream_t s);
 hipError_t launch_cvt16(const float* src, uint16_t* dst, long n, hipStream_t s);
 // dst (cols x rows) = bf16(src (rows x cols))^T
 hipError_t launch_cvt16_t(const float* src, uint16_t* dst, long rows, long cols, hipStream_t s);
+// both: dst = bf16(src), dst_t = bf16(src)^T, one read of src
+hipError_t launch_cvt16_both(const float* src, uint16_t* dst, uint16_t* dst_t, long rows, long cols, hipStream_t s);
 // Elements of the LDS tile of the tiled permutation (at most).
 constexpr int kTilePermElems = 8192;
 hipError_t launch_tile_permute(const TilePermArgs& p, hipStream_t s);

@@ -4,13 +4,15 @@ sign, so each bond's columns are aligned to the oracle's before the
 comparison, the next core's rows flipped with them), the reconstruction and
 Algorithm 1's error bound, on the paper's Example 2 shapes, truncated
 low-rank tensors, wide and tall unfoldings, and degenerate cases."""
+import math
+
 import numpy as np
 import pytest
 
 from oracle import tt_oracle as O
 from ttgen import configs as C
 
-from helpers import TOL, rel_err, to_np
+from helpers import TOL, rel_err, to_gpu, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -104,7 +106,8 @@ def test_svd_fp32(ttc):
     """FP32 tensor, FP32 storage with FP64 dot products: ranks equal the
     oracle's (on the FP32 values), reconstruction within the FP32 bound,
     left cores orthonormal to the Jacobi threshold (pairs stop rotating at
-    |a_i . a_j| <= L u ||a_i|| ||a_j||, about 3e-5 for L = 480 in FP32)."""
+    |a_i . a_j| <= 32 u sqrt(L) ||a_i|| ||a_j||, about 4e-5 for L = 480 in
+    FP32)."""
     X = _dense(5, (12, 10, 8, 6))
     xg, Xs = _upload(X, "f32")
     cores = [to_np(c) for c in ttc.tt_svd(xg)]
@@ -201,3 +204,34 @@ def test_round_fp32_and_cap(ttc):
     xg, _ = to_gpu(x, "f64")
     cores = ttc.tt_round(xg, max_rank=2)
     assert [int(c.shape[0]) for c in cores] + [1] == [1, 2, 2, 2, 1]
+
+
+def test_round_mpo8_rank1024(ttc):
+    """The order-8 MPO x TT product (BF16 inputs, FP32 cores of ranks 1024)
+    rounded at eps = 0.3 on the GPU: every core unfolding is 1024 x 32768,
+    so each Jacobi SVD rotates 1024 vectors.  Checked at full size through
+    properties (no dense tensor exists: 32^8 entries): ranks below 1024;
+    cores 0..6 left-orthonormal to the FP32 Jacobi threshold (32 u sqrt(L),
+    about 3.5e-4 at L = 32768); and Algorithm 1's bound through the
+    inner products of the library, ||X - X'||^2 = <X, X> - 2 <X, X'> +
+    <X', X'> <= eps^2 ||X||^2."""
+    import torch
+    sw, sv = C.mpo8_shapes()
+    wg, _ = to_gpu(C.gen_tt_np(C.SEED_MPO8, 1, sw), "bf16")
+    vg, _ = to_gpu(C.gen_tt_np(C.SEED_MPO8, 2, sv), "bf16")
+    x = ttc.ttm_apply(wg, vg)
+    eps = 0.3
+    r = ttc.tt_round(x, eps=eps)
+    ranks = [int(c.shape[0]) for c in r] + [1]
+    print("rounded ranks", ranks)
+    assert all(1 <= a <= 1024 for a in ranks) and ranks[1] < 1024
+    for G in r[:-1]:
+        U = G.reshape(-1, G.shape[2]).to(torch.float64)
+        I = torch.eye(U.shape[1], dtype=torch.float64, device=U.device)
+        assert float(torch.max(torch.abs(U.T @ U - I))) <= 1e-3
+    xx = ttc.tt_contract_inner(x, x).item()
+    xr = ttc.tt_contract_inner(x, r).item()
+    rr = ttc.tt_contract_inner(r, r).item()
+    err2 = xx - 2 * xr + rr
+    print("relative error", math.sqrt(max(err2, 0.0) / xx))
+    assert err2 <= (eps ** 2 + 1e-3) * xx
