@@ -553,12 +553,19 @@ def main():
         beside["layer4_f32_fwd_bwd_ms"] = round(part_ms["layer4"], 4)
         beside["layer4_f32_fwd_ms"] = round(fwd_ms, 4)
         # the core-by-core schedule (the method applied to the batch): one
-        # GEMM per core, 4x the FLOPs of the dense schedule on this shape
+        # GEMM per core, 4x the FLOPs of the dense schedule on this shape;
+        # forward + backward keep the forward's intermediates for the
+        # backward (schedule cores_saved, one workspace for both calls)
+        cws = torch.empty(ttc.ttm_apply_dense_query(d["w"], 8192, "f32", "cores_saved", backward=True),
+                          dtype=torch.uint8, device=d["X"].device)
+
         def cores(bwd):
-            Y = ttc.ttm_apply_dense(d["w"], d["X"], sched="cores")
-            if bwd:
-                _, dY = ttc.ttc_mse_loss(Y, d["T"])
-                ttc.ttm_apply_dense_bwd(d["w"], d["X"], dY, sched="cores")
+            if not bwd:
+                ttc.ttm_apply_dense(d["w"], d["X"], sched="cores")
+                return
+            Y = ttc.ttm_apply_dense(d["w"], d["X"], sched="cores_saved", ws=cws)
+            _, dY = ttc.ttc_mse_loss(Y, d["T"])
+            ttc.ttm_apply_dense_bwd(d["w"], d["X"], dY, sched="cores_saved", ws=cws)
 
         for bwd, key in ((False, "layer4_cores_f32_fwd_ms"), (True, "layer4_cores_f32_fwd_bwd_ms")):
             cores(bwd)

@@ -86,8 +86,20 @@ typedef enum { TTC_JUNCTION = 0, TTC_NATURAL_TT = 1, TTC_DENSE = 2 } ttc_form;
 
 /* Schedule of a TT-matrix x dense-batch product.  CORES: contract the batch
  * with one core at a time.  DENSE: rebuild the dense matrix from the cores,
- * then one matrix product.  AUTO picks the smaller FLOP count. */
-typedef enum { TTC_SCHED_AUTO = 0, TTC_SCHED_CORES = 1, TTC_SCHED_DENSE = 2 } ttc_sched;
+ * then one matrix product.  AUTO picks the smaller FLOP count.
+ * CORES_SAVED: CORES whose forward keeps every intermediate (one per core,
+ * batch x prod(I_<k) x prod(J_>=k) x R_k elements) and the permuted cores in
+ * the workspace, and whose backward reads them there instead of recomputing
+ * the forward: the backward must get the same workspace, unmodified, with
+ * the same cores, x, batch and prec as the forward that filled it (the
+ * caller's contract, as for activations saved for a backward pass; it is
+ * not checked).  Both directions query the backward's workspace size. */
+typedef enum {
+  TTC_SCHED_AUTO = 0,
+  TTC_SCHED_CORES = 1,
+  TTC_SCHED_DENSE = 2,
+  TTC_SCHED_CORES_SAVED = 3
+} ttc_sched;
 
 /* TT tensor descriptor. */
 typedef struct {

@@ -21,6 +21,7 @@ from .api import (  # noqa: F401
     ttm_apply,
     ttm_apply_dense,
     ttm_apply_dense_bwd,
+    ttm_apply_dense_query,
     version,
 )
 from .autograd import TTInner, TTLinear, tt_inner, tt_linear  # noqa: F401

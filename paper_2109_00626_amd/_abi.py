@@ -18,7 +18,7 @@ STATUS_NAMES = {
 TTC_F64, TTC_F32, TTC_BF16 = 0, 1, 2
 PREC = {"auto": 0, "f64": 1, "f32": 2, "bf16": 3}
 FORM = {"junction": 0, "natural": 1, "dense": 2}
-SCHED = {"auto": 0, "cores": 1, "dense": 2}
+SCHED = {"auto": 0, "cores": 1, "dense": 2, "cores_saved": 3}
 OP_INNER, OP_SUFFIX2 = 1, 2
 
 

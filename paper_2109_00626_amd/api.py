@@ -303,11 +303,32 @@ def ttm_apply(w, v, prec: str = "auto"):
     return cores
 
 
-def ttm_apply_dense(w, x: torch.Tensor, prec: str = "auto", sched: str = "auto") -> torch.Tensor:
-    """Y = X W^T for a batch X (batch x prod J, little-endian rows)."""
+def ttm_apply_dense_query(w, batch: int, prec: str = "auto", sched: str = "auto", backward: bool = False) -> int:
+    """Workspace bytes of ttm_apply_dense (backward False) or its backward."""
+    dm = TTMDesc(w, "w")
+    need = c_size_t(0)
+    _check(_lib.ttm_apply_dense_query(dm.ref, int(batch), _abi.PREC[prec], _abi.SCHED[sched], int(backward),
+                                      byref(need)))
+    return need.value
+
+
+def _layer_ws(ws, need: int, dev):
+    if ws is None:
+        return _ws(need, dev)
+    if ws.device != dev or not ws.is_contiguous() or ws.numel() * ws.element_size() < need:
+        raise ValueError("ws must be a contiguous tensor of at least the queried bytes on the cores' device")
+    return ws
+
+
+def ttm_apply_dense(w, x: torch.Tensor, prec: str = "auto", sched: str = "auto", ws=None) -> torch.Tensor:
+    """Y = X W^T for a batch X (batch x prod J, little-endian rows).  ws:
+    the workspace (a device tensor of at least ttm_apply_dense_query bytes;
+    required for sched "cores_saved", whose backward reads it)."""
     dm = TTMDesc(w, "w")
     if x.dtype != torch.float32 or not x.is_contiguous() or x.dim() != 2 or x.device != dm.device:
         raise ValueError("x must be a contiguous 2-D float32 tensor on the cores' device")
+    if sched == "cores_saved" and ws is None:
+        raise ValueError('sched "cores_saved" needs a workspace kept for the backward')
     B = int(x.shape[0])
     need = c_size_t(0)
     p, s = _abi.PREC[prec], _abi.SCHED[sched]
@@ -316,17 +337,19 @@ def ttm_apply_dense(w, x: torch.Tensor, prec: str = "auto", sched: str = "auto")
     for r in dm.rows:
         rows *= r
     y = torch.empty(B, rows, dtype=torch.float32, device=dm.device)
-    ws = _ws(need.value, dm.device)
+    ws = _layer_ws(ws, need.value, dm.device)
     _check(_lib.ttm_apply_dense(dm.ref, _ptr(x), B, _ptr(y), p, s, _ptr(ws), need.value, _stream(dm.device)))
     return y
 
 
 def ttm_apply_dense_bwd(w, x: torch.Tensor, dy: torch.Tensor, prec: str = "auto", sched: str = "auto",
-                        need_dx: bool = True, need_dw: bool = True):
+                        need_dx: bool = True, need_dw: bool = True, ws=None):
     dm = TTMDesc(w, "w")
     for t in (x, dy):
         if t.dtype != torch.float32 or not t.is_contiguous() or t.dim() != 2 or t.device != dm.device:
             raise ValueError("x and dy must be contiguous 2-D float32 tensors on the cores' device")
+    if sched == "cores_saved" and ws is None:
+        raise ValueError('sched "cores_saved" needs the forward\'s workspace')
     B = int(x.shape[0])
     need = c_size_t(0)
     p, s = _abi.PREC[prec], _abi.SCHED[sched]
@@ -334,7 +357,7 @@ def ttm_apply_dense_bwd(w, x: torch.Tensor, dy: torch.Tensor, prec: str = "auto"
     dx = torch.empty_like(x) if need_dx else None
     dcores = [torch.empty(c.shape, dtype=torch.float32, device=dm.device) for c in w] if need_dw else None
     dptr = (c_void_p * len(w))(*[c.data_ptr() for c in dcores]) if need_dw else None
-    ws = _ws(need.value, dm.device)
+    ws = _layer_ws(ws, need.value, dm.device)
     _check(_lib.ttm_apply_dense_bwd(dm.ref, _ptr(x), _ptr(dy), B, _ptr(dx), dptr, p, s, _ptr(ws), need.value,
                                     _stream(dm.device)))
     return dx, dcores

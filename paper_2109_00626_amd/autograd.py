@@ -3,7 +3,9 @@
 TTInner: z = <X, Y> with gradients for every core of X and Y (adjoint
 sweeps that keep every c-th interface and recompute the rest).
 TTLinear: y = W x for a TT-matrix W, gradients for the input batch and every
-core.  Both save only their inputs."""
+core.  Both save only their inputs, except TTLinear with the schedule
+"cores_saved", which also keeps the forward's workspace (its per-core
+intermediates) for the backward."""
 from __future__ import annotations
 
 import torch
@@ -41,14 +43,19 @@ class TTLinear(torch.autograd.Function):
     def forward(ctx, x, prec: str, sched: str, *cores):
         ctx.prec, ctx.sched = prec, sched
         ctx.save_for_backward(x, *cores)
-        return api.ttm_apply_dense(list(cores), x, prec=prec, sched=sched)
+        ctx.ws = None
+        if sched == "cores_saved":
+            need = api.ttm_apply_dense_query(list(cores), x.shape[0], prec, sched, backward=True)
+            ctx.ws = torch.empty(max(need, 1), dtype=torch.uint8, device=x.device)
+        return api.ttm_apply_dense(list(cores), x, prec=prec, sched=sched, ws=ctx.ws)
 
     @staticmethod
     def backward(ctx, dy):
         x, *cores = ctx.saved_tensors
         dx, dcores = api.ttm_apply_dense_bwd(list(cores), x, dy.contiguous(), prec=ctx.prec, sched=ctx.sched,
                                              need_dx=ctx.needs_input_grad[0],
-                                             need_dw=any(ctx.needs_input_grad[3:]))
+                                             need_dw=any(ctx.needs_input_grad[3:]), ws=ctx.ws)
+        ctx.ws = None
         if dcores is None:
             dcores = [None] * len(cores)
         return (dx, None, None, *dcores)

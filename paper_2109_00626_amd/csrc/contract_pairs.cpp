@@ -341,7 +341,6 @@ ttc_status tt_contract_pairs(const ttc_tt* x, const ttc_tt* y, const int32_t* xm
     o.d1 = c.d1;
     o.kg = c.kg;
     o.kd = c.kd;
-    o.line_begin = lines;
     o.src = c.src;
     o.dst = dst[m];
     lines += c.d0 * c.n;

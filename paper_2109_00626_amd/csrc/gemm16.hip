@@ -168,53 +168,84 @@ __global__ __launch_bounds__(256) void cvt16_kernel(const float* __restrict__ sr
   }
 }
 
-// dst[c * rows + r] = bf16(src[r * cols + c]): 64 x 64 tiles through LDS,
-// rows of the source read and rows of the destination written contiguously.
-__global__ __launch_bounds__(256) void cvt16_t_kernel(const float* __restrict__ src, uint16_t* __restrict__ dst,
-                                                      long rows, long cols) {
+// dst[c * rows + r] = bf16(src[r * cols + c]) (and, BOTH, dst[r * cols + c]
+// = bf16(src[r * cols + c])): 64 x 64 tiles through LDS (pitch 65: the
+// column reads are conflict-free), the source read as 16-byte runs of a
+// row, the transposed copy written as 16-byte runs (eight elements) of a
+// destination row.  VEC: cols a multiple of 4 and rows of 8 (and aligned
+// buffers), else one element per access.
+template <bool BOTH, bool VEC>
+__global__ __launch_bounds__(256) void cvt16_tr_kernel(const float* __restrict__ src, uint16_t* __restrict__ dst,
+                                                       uint16_t* __restrict__ dst_t, long rows, long cols) {
   __shared__ float tile[64][65];
   const long r0 = (long)blockIdx.x * 64, c0 = (long)blockIdx.y * 64;
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // 64 x 4
+  if (VEC) {
+    // 16 lanes per source row (four columns each), 16 rows per pass
+    const int tc = (threadIdx.x & 15) * 4, tr = threadIdx.x >> 4;
+#pragma unroll
+    for (int q = 0; q < 64; q += 16) {
+      const long r = r0 + tr + q, c = c0 + tc;
+      f32x4 v = {0.f, 0.f, 0.f, 0.f};
+      if (r < rows && c < cols) {
+        v = *reinterpret_cast<const f32x4*>(src + r * cols + c);
+        if (BOTH) {
+          uint2 w;
+          w.x = (uint32_t)f32_to_bf16(v[0]) | ((uint32_t)f32_to_bf16(v[1]) << 16);
+          w.y = (uint32_t)f32_to_bf16(v[2]) | ((uint32_t)f32_to_bf16(v[3]) << 16);
+          *reinterpret_cast<uint2*>(dst + r * cols + c) = w;
+        }
+      }
+#pragma unroll
+      for (int x = 0; x < 4; ++x) tile[tr + q][tc + x] = v[x];
+    }
+    __syncthreads();
+    // 8 lanes per destination row (eight source rows each), 32 rows per pass
+    const int dr = (threadIdx.x & 7) * 8, dc = threadIdx.x >> 3;
+#pragma unroll
+    for (int q = 0; q < 64; q += 32) {
+      const long c = c0 + dc + q, r = r0 + dr;
+      if (c < cols && r < rows) {
+        u32x4 w;
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+          w[x] = (uint32_t)f32_to_bf16(tile[dr + 2 * x][dc + q]) |
+                 ((uint32_t)f32_to_bf16(tile[dr + 2 * x + 1][dc + q]) << 16);
+        *reinterpret_cast<u32x4*>(dst_t + c * rows + r) = w;
+      }
+    }
+  } else {
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // 64 x 4
 #pragma unroll 4
-  for (int q = 0; q < 64; q += 4) {
-    const long r = r0 + ty + q, c = c0 + tx;
-    tile[ty + q][tx] = (r < rows && c < cols) ? src[r * cols + c] : 0.f;
-  }
-  __syncthreads();
+    for (int q = 0; q < 64; q += 4) {
+      const long r = r0 + ty + q, c = c0 + tx;
+      const bool in = r < rows && c < cols;
+      const float v = in ? src[r * cols + c] : 0.f;
+      tile[ty + q][tx] = v;
+      if (BOTH && in) dst[r * cols + c] = f32_to_bf16(v);
+    }
+    __syncthreads();
 #pragma unroll 4
-  for (int q = 0; q < 64; q += 4) {
-    const long c = c0 + ty + q, r = r0 + tx;
-    if (r < rows && c < cols) dst[c * rows + r] = f32_to_bf16(tile[tx][ty + q]);
+    for (int q = 0; q < 64; q += 4) {
+      const long c = c0 + ty + q, r = r0 + tx;
+      if (r < rows && c < cols) dst_t[c * rows + r] = f32_to_bf16(tile[tx][ty + q]);
+    }
   }
 }
 
-// Both copies of one source in one pass: dst (rows x cols) = bf16(src) and
-// dst_t (cols x rows) = bf16(src)^T.
-__global__ __launch_bounds__(256) void cvt16_both_kernel(const float* __restrict__ src, uint16_t* __restrict__ dst,
-                                                         uint16_t* __restrict__ dst_t, long rows, long cols) {
-  __shared__ float tile[64][65];
-  const long r0 = (long)blockIdx.x * 64, c0 = (long)blockIdx.y * 64;
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // 64 x 4
-#pragma unroll 4
-  for (int q = 0; q < 64; q += 4) {
-    const long r = r0 + ty + q, c = c0 + tx;
-    const bool in = r < rows && c < cols;
-    const float v = in ? src[r * cols + c] : 0.f;
-    tile[ty + q][tx] = v;
-    if (in) dst[r * cols + c] = f32_to_bf16(v);
-  }
-  __syncthreads();
-#pragma unroll 4
-  for (int q = 0; q < 64; q += 4) {
-    const long c = c0 + ty + q, r = r0 + tx;
-    if (r < rows && c < cols) dst_t[c * rows + r] = f32_to_bf16(tile[tx][ty + q]);
-  }
+template <bool BOTH>
+static void launch_tr(const float* src, uint16_t* dst, uint16_t* dst_t, long rows, long cols, hipStream_t s) {
+  const dim3 grid((unsigned)((rows + 63) / 64), (unsigned)((cols + 63) / 64));
+  const bool vec = cols % 4 == 0 && rows % 8 == 0 && ((uintptr_t)src & 15) == 0 && ((uintptr_t)dst_t & 15) == 0 &&
+                   (!BOTH || ((uintptr_t)dst & 7) == 0);
+  if (vec)
+    hipLaunchKernelGGL((cvt16_tr_kernel<BOTH, true>), grid, dim3(256), 0, s, src, dst, dst_t, rows, cols);
+  else
+    hipLaunchKernelGGL((cvt16_tr_kernel<BOTH, false>), grid, dim3(256), 0, s, src, dst, dst_t, rows, cols);
 }
 
 hipError_t launch_cvt16_both(const float* src, uint16_t* dst, uint16_t* dst_t, long rows, long cols, hipStream_t s) {
   if (rows <= 0 || cols <= 0) return hipSuccess;
-  const dim3 grid((unsigned)((rows + 63) / 64), (unsigned)((cols + 63) / 64));
-  hipLaunchKernelGGL(cvt16_both_kernel, grid, dim3(256), 0, s, src, dst, dst_t, rows, cols);
+  launch_tr<true>(src, dst, dst_t, rows, cols, s);
   return hipGetLastError();
 }
 
@@ -239,8 +270,7 @@ hipError_t launch_cvt16(const float* src, uint16_t* dst, long n, hipStream_t s) 
 
 hipError_t launch_cvt16_t(const float* src, uint16_t* dst, long rows, long cols, hipStream_t s) {
   if (rows <= 0 || cols <= 0) return hipSuccess;
-  const dim3 grid((unsigned)((rows + 63) / 64), (unsigned)((cols + 63) / 64));
-  hipLaunchKernelGGL(cvt16_t_kernel, grid, dim3(256), 0, s, src, dst, rows, cols);
+  launch_tr<false>(src, nullptr, dst, rows, cols, s);
   return hipGetLastError();
 }
 

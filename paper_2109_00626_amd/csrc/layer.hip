@@ -22,7 +22,9 @@
 //
 // GEMM: 128 x 128 output tile per 256-thread workgroup, each wave a 64 x 64
 // quarter on 16x16 MFMA tiles (FP32: 16x16x4, BF16: 16x16x32 with FP32
-// accumulation), operands staged through double-buffered LDS.  Global
+// accumulation), operands staged through double-buffered LDS; thin tiles
+// (32 x 128, 128 x 32, 128 x 64) for the rank-sized products of the core
+// chain, so that a side of 32 is not padded to 128.  Global
 // operands are FP32; the BF16 variant rounds them (RNE) while staging.
 // Optional split-K writes FP32 partial slabs that a second kernel sums in a
 // fixed order (deterministic).
@@ -31,8 +33,6 @@
 
 namespace ttc {
 
-#define GBM 128
-#define GBN 128
 #define GPAD 4
 
 template <bool BF16>
@@ -46,19 +46,30 @@ struct GemmCfg<true> {
   static constexpr int BK = 64;
 };
 
-// Number of float4 loads per thread for one operand tile.
-template <bool BF16>
+// Output tile shapes (TM x TN per 256-thread workgroup): the square tile
+// and thin ones for products with a side of 32 or 64 (rank-sized), each
+// wave computing a (TM / WM) x (TN / WN) block of FI x FJ MFMA tiles.
+template <int TM, int TN>
+struct GemmShape {
+  static constexpr int WN = (TM == 128 && TN == 32) ? 1 : (TM == 32 ? 4 : 2);
+  static constexpr int WM = 4 / WN;
+  static constexpr int FI = TM / WM / 16, FJ = TN / WN / 16;
+};
+
+// Number of float4 loads per thread for one operand tile of ROWS rows.
+template <bool BF16, int ROWS>
 __device__ constexpr int loads_per_thread() {
-  return (GBM * GemmCfg<BF16>::BK / 4) / 256;
+  return (ROWS * GemmCfg<BF16>::BK / 4) / 256;
 }
 
-// Load one operand tile (rows = the operand's M or N dimension, 128 of them;
-// columns = 32/64 of K) into registers.  kc: K is the contiguous dimension.
-template <bool BF16, bool KC>
+// Load one operand tile (rows = the operand's M or N dimension, ROWS of
+// them; columns = 32/64 of K) into registers.  kc: K is the contiguous
+// dimension.
+template <bool BF16, bool KC, int ROWS>
 __device__ __forceinline__ void load_tile(const float* P, long ld, int row0, int nrows, int k0, int K, bool vec,
                                           f32x4* r) {
   constexpr int BK = GemmCfg<BF16>::BK;
-  constexpr int L = loads_per_thread<BF16>();
+  constexpr int L = loads_per_thread<BF16, ROWS>();
 #pragma unroll
   for (int it = 0; it < L; ++it) {
     const int e = threadIdx.x + 256 * it;
@@ -67,8 +78,8 @@ __device__ __forceinline__ void load_tile(const float* P, long ld, int row0, int
       row = e / (BK / 4);
       kk = (e % (BK / 4)) * 4;
     } else {
-      kk = e / (GBM / 4);
-      row = (e % (GBM / 4)) * 4;
+      kk = e / (ROWS / 4);
+      row = (e % (ROWS / 4)) * 4;
     }
     f32x4 v = {0.f, 0.f, 0.f, 0.f};
     if (KC) {
@@ -100,12 +111,13 @@ __device__ __forceinline__ void load_tile(const float* P, long ld, int row0, int
   }
 }
 
-// Store staged registers into LDS.  FP32 layout: S[k][row] (pitch GBM+GPAD);
-// BF16 layout: S[row][k] (pitch BK+8, k contiguous for 16-byte fragments).
-template <bool BF16, bool KC>
+// Store staged registers into LDS.  FP32 layout: S[k][row] (pitch
+// ROWS+GPAD); BF16 layout: S[row][k] (pitch BK+8, k contiguous for 16-byte
+// fragments).
+template <bool BF16, bool KC, int ROWS>
 __device__ __forceinline__ void store_tile(void* S, const f32x4* r) {
   constexpr int BK = GemmCfg<BF16>::BK;
-  constexpr int L = loads_per_thread<BF16>();
+  constexpr int L = loads_per_thread<BF16, ROWS>();
 #pragma unroll
   for (int it = 0; it < L; ++it) {
     const int e = threadIdx.x + 256 * it;
@@ -114,16 +126,16 @@ __device__ __forceinline__ void store_tile(void* S, const f32x4* r) {
       row = e / (BK / 4);
       kk = (e % (BK / 4)) * 4;
     } else {
-      kk = e / (GBM / 4);
-      row = (e % (GBM / 4)) * 4;
+      kk = e / (ROWS / 4);
+      row = (e % (ROWS / 4)) * 4;
     }
     if (!BF16) {
       float* s = reinterpret_cast<float*>(S);
       if (KC) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) s[(kk + q) * (GBM + GPAD) + row] = r[it][q];
+        for (int q = 0; q < 4; ++q) s[(kk + q) * (ROWS + GPAD) + row] = r[it][q];
       } else {
-        *reinterpret_cast<f32x4*>(s + kk * (GBM + GPAD) + row) = r[it];
+        *reinterpret_cast<f32x4*>(s + kk * (ROWS + GPAD) + row) = r[it];
       }
     } else {
       uint16_t* s = reinterpret_cast<uint16_t*>(S);
@@ -141,23 +153,25 @@ __device__ __forceinline__ void store_tile(void* S, const f32x4* r) {
   }
 }
 
-template <bool BF16>
+template <bool BF16, int ROWS>
 __host__ __device__ constexpr int tile_elems() {
-  return BF16 ? GBM * (GemmCfg<true>::BK + 8) : GemmCfg<false>::BK * (GBM + GPAD);
+  return BF16 ? ROWS * (GemmCfg<true>::BK + 8) : GemmCfg<false>::BK * (ROWS + GPAD);
 }
 
-template <bool A_KC, bool B_KC, bool BF16>
+template <bool A_KC, bool B_KC, bool BF16, int TM, int TN>
 __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
   extern __shared__ __align__(16) unsigned char smem[];
+  typedef GemmShape<TM, TN> S;
+  constexpr int FI = S::FI, FJ = S::FJ;
   constexpr int BK = GemmCfg<BF16>::BK;
-  constexpr int L = loads_per_thread<BF16>();
+  constexpr int LA = loads_per_thread<BF16, TM>(), LB = loads_per_thread<BF16, TN>();
   constexpr int esz = BF16 ? 2 : 4;
-  constexpr int TE = tile_elems<BF16>();
-  unsigned char* As = smem;                    // [2][TE]
-  unsigned char* Bs = smem + 2 * TE * esz;     // [2][TE]
-  const int tn = (g.N + GBN - 1) / GBN;
+  constexpr int TA = tile_elems<BF16, TM>(), TB = tile_elems<BF16, TN>();
+  unsigned char* As = smem;                    // [2][TA]
+  unsigned char* Bs = smem + 2 * TA * esz;     // [2][TB]
+  const int tn = (g.N + TN - 1) / TN;
   const int bm = blockIdx.x / tn, bn = blockIdx.x - bm * tn;
-  const int m0 = bm * GBM, n0 = bn * GBN;
+  const int m0 = bm * TM, n0 = bn * TN;
   // K range of this split
   const int kper = ((g.K + g.splits - 1) / g.splits + BK - 1) / BK * BK;
   const int kbeg = blockIdx.y * kper;
@@ -165,67 +179,69 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
   const int nk = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave / S::WN, wn = wave % S::WN;
   const int li = lane & 15, lg = lane >> 4;
-  f32x4 acc[4][4];
+  const int am = wm * FI * 16, bn0 = wn * FJ * 16;  // the wave's block
+  f32x4 acc[FI][FJ];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < FI; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < FJ; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  f32x4 ra[L], rb[L];
+  f32x4 ra[LA], rb[LB];
   if (nk > 0) {
-    load_tile<BF16, A_KC>(g.A, g.lda, m0, g.M, kbeg, kend, g.vec_a, ra);
-    load_tile<BF16, B_KC>(g.B, g.ldb, n0, g.N, kbeg, kend, g.vec_b, rb);
-    store_tile<BF16, A_KC>(As, ra);
-    store_tile<BF16, B_KC>(Bs, rb);
+    load_tile<BF16, A_KC, TM>(g.A, g.lda, m0, g.M, kbeg, kend, g.vec_a, ra);
+    load_tile<BF16, B_KC, TN>(g.B, g.ldb, n0, g.N, kbeg, kend, g.vec_b, rb);
+    store_tile<BF16, A_KC, TM>(As, ra);
+    store_tile<BF16, B_KC, TN>(Bs, rb);
   }
   __syncthreads();
   for (int kt = 0; kt < nk; ++kt) {
     const int buf = kt & 1;
     if (kt + 1 < nk) {
       const int k0 = kbeg + (kt + 1) * BK;
-      load_tile<BF16, A_KC>(g.A, g.lda, m0, g.M, k0, kend, g.vec_a, ra);
-      load_tile<BF16, B_KC>(g.B, g.ldb, n0, g.N, k0, kend, g.vec_b, rb);
+      load_tile<BF16, A_KC, TM>(g.A, g.lda, m0, g.M, k0, kend, g.vec_a, ra);
+      load_tile<BF16, B_KC, TN>(g.B, g.ldb, n0, g.N, k0, kend, g.vec_b, rb);
     }
     if (!BF16) {
-      const float* a_s = reinterpret_cast<const float*>(As) + buf * TE;
-      const float* b_s = reinterpret_cast<const float*>(Bs) + buf * TE;
+      const float* a_s = reinterpret_cast<const float*>(As) + buf * TA;
+      const float* b_s = reinterpret_cast<const float*>(Bs) + buf * TB;
 #pragma unroll
       for (int kk = 0; kk < BK; kk += 4) {
-        float av[4], bv[4];
+        float av[FI], bv[FJ];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) av[i] = a_s[(kk + lg) * (GBM + GPAD) + wm * 64 + 16 * i + li];
+        for (int i = 0; i < FI; ++i) av[i] = a_s[(kk + lg) * (TM + GPAD) + am + 16 * i + li];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) bv[j] = b_s[(kk + lg) * (GBM + GPAD) + wn * 64 + 16 * j + li];
+        for (int j = 0; j < FJ; ++j) bv[j] = b_s[(kk + lg) * (TN + GPAD) + bn0 + 16 * j + li];
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < FI; ++i)
 #pragma unroll
-          for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc[i][j], 0, 0, 0);
+          for (int j = 0; j < FJ; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc[i][j], 0, 0, 0);
       }
     } else {
-      const uint16_t* a_s = reinterpret_cast<const uint16_t*>(As) + buf * TE;
-      const uint16_t* b_s = reinterpret_cast<const uint16_t*>(Bs) + buf * TE;
+      const uint16_t* a_s = reinterpret_cast<const uint16_t*>(As) + buf * TA;
+      const uint16_t* b_s = reinterpret_cast<const uint16_t*>(Bs) + buf * TB;
       constexpr int P = BK + 8;
 #pragma unroll
       for (int kk = 0; kk < BK; kk += 32) {
-        bf16x8 av[4], bv[4];
+        bf16x8 av[FI], bv[FJ];
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-          av[i] = *reinterpret_cast<const bf16x8*>(a_s + (wm * 64 + 16 * i + li) * P + kk + 8 * lg);
+        for (int i = 0; i < FI; ++i)
+          av[i] = *reinterpret_cast<const bf16x8*>(a_s + (am + 16 * i + li) * P + kk + 8 * lg);
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-          bv[j] = *reinterpret_cast<const bf16x8*>(b_s + (wn * 64 + 16 * j + li) * P + kk + 8 * lg);
+        for (int j = 0; j < FJ; ++j)
+          bv[j] = *reinterpret_cast<const bf16x8*>(b_s + (bn0 + 16 * j + li) * P + kk + 8 * lg);
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < FI; ++i)
 #pragma unroll
-          for (int j = 0; j < 4; ++j)
+          for (int j = 0; j < FJ; ++j)
             acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv[j], acc[i][j], 0, 0, 0);
       }
     }
     if (kt + 1 < nk) {
-      store_tile<BF16, A_KC>(As + (buf ^ 1) * TE * esz, ra);
-      store_tile<BF16, B_KC>(Bs + (buf ^ 1) * TE * esz, rb);
+      store_tile<BF16, A_KC, TM>(As + (buf ^ 1) * TA * esz, ra);
+      store_tile<BF16, B_KC, TN>(Bs + (buf ^ 1) * TB * esz, rb);
     }
     __syncthreads();
   }
@@ -234,62 +250,65 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
   const float alpha = g.splits > 1 ? 1.f : g.alpha;
   if (g.mapped) {
     // relayout store: row and column parts of each address computed once
-    long roff[4][4], coff[4];
+    long roff[FI][4], coff[FJ];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < FI; ++i)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const long m = m0 + wm * 64 + 16 * i + 4 * lg + v;
+        const long m = m0 + am + 16 * i + 4 * lg + v;
         const long q = m % g.map.mr0, t = m / g.map.mr0;
         roff[i][v] = (t / g.map.mr1) * g.map.ms2 + (t % g.map.mr1) * g.map.ms1 + q * g.map.ms0;
       }
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const long n = n0 + wn * 64 + 16 * j + li;
+    for (int j = 0; j < FJ; ++j) {
+      const long n = n0 + bn0 + 16 * j + li;
       coff[j] = (n / g.map.nr0) * g.map.ns1 + (n % g.map.nr0) * g.map.ns0;
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < FI; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
+      for (int j = 0; j < FJ; ++j)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int m = m0 + wm * 64 + 16 * i + 4 * lg + v;
-          const int n = n0 + wn * 64 + 16 * j + li;
+          const int m = m0 + am + 16 * i + 4 * lg + v;
+          const int n = n0 + bn0 + 16 * j + li;
           if (m < g.M && n < g.N) g.C[roff[i][v] + coff[j]] = g.alpha * acc[i][j][v];
         }
     return;
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < FI; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < FJ; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int m = m0 + wm * 64 + 16 * i + 4 * lg + v;
-        const int n = n0 + wn * 64 + 16 * j + li;
+        const int m = m0 + am + 16 * i + 4 * lg + v;
+        const int n = n0 + bn0 + 16 * j + li;
         if (m < g.M && n < g.N) C[(long)m * ldc + n] = alpha * acc[i][j][v];
       }
 }
 
-// C = alpha * (sum over z of slab[z]): 32 consecutive elements per workgroup,
-// eight lanes per element, each lane summing every eighth partial in order,
-// then the eight sums added in lane order (a fixed order: deterministic).
+// C = alpha * (sum over z of slab[z]): 256 / ZL consecutive elements per
+// workgroup, ZL lanes per element, each lane summing every ZL-th partial in
+// order, then the ZL sums added in lane order (a fixed order:
+// deterministic).  ZL = 8, or 64 for many partials of a small output.
+template <int ZL>
 __global__ __launch_bounds__(256) void splitk_reduce_kernel(const float* slab, int splits, int M, int N, float alpha,
                                                             float* C, long ldc) {
-  __shared__ float part[8][33];
-  const int el = threadIdx.x & 31, zl = threadIdx.x >> 5;
+  constexpr int EL = 256 / ZL;
+  __shared__ float part[ZL][EL + 1];
+  const int el = threadIdx.x % EL, zl = threadIdx.x / EL;
   const long MN = (long)M * N;
-  const long e = (long)blockIdx.x * 32 + el;
+  const long e = (long)blockIdx.x * EL + el;
   float s = 0.f;
   if (e < MN)
-    for (int z = zl; z < splits; z += 8) s += slab[(long)z * MN + e];
+    for (int z = zl; z < splits; z += ZL) s += slab[(long)z * MN + e];
   part[zl][el] = s;
   __syncthreads();
   if (zl == 0 && e < MN) {
     float t = part[0][el];
 #pragma unroll
-    for (int q = 1; q < 8; ++q) t += part[q][el];
+    for (int q = 1; q < ZL; ++q) t += part[q][el];
     const long m = e / N, n = e - m * N;
     C[m * ldc + n] = alpha * t;
   }
@@ -340,11 +359,15 @@ __global__ __launch_bounds__(256) void permute_kernel(PermArgs p) {
 // Tiled form of the same permutation (see TilePermArgs): the tile is read
 // with the source layout's contiguous digits fastest, transposed through
 // LDS (pitch Bp + 1: conflict-free both ways) and written with the
-// destination layout's contiguous digits fastest.
+// destination layout's contiguous digits fastest; V = 4: each thread moves
+// four consecutive elements of a run with one 16-byte global access (8
+// bytes for a BF16 destination).
+template <int V, bool OUT16>
 __global__ __launch_bounds__(256) void tile_permute_kernel(TilePermArgs p) {
   __shared__ float tile[kTilePermElems + 64];
   __shared__ long offP[256];
-  const int Bp = p.Bp, Bm = p.Bm, pitch = Bp + 1, n = Bp * Bm;
+  const int Bp = p.Bp, Bm = p.Bm, pitch = Bp + 1;
+  const int gp = Bp / V, gm = Bm / V, ng = Bp * Bm / V;
   // tile base offsets from the outer digits
   long rem = blockIdx.x, baseP = 0, baseM = 0;
   for (int q = 0; q < p.nout; ++q) {
@@ -365,27 +388,64 @@ __global__ __launch_bounds__(256) void tile_permute_kernel(TilePermArgs p) {
   __syncthreads();
   if (p.dir == 0) {
     // pair-mode -> matrix: read runs of Bp, write runs of Bm
-    for (int e = threadIdx.x; e < n; e += 256) {
-      const int q = e % Bp, c = e / Bp;
-      tile[c * pitch + q] = p.src[baseP + offP[c] + q];
+    for (int g = threadIdx.x; g < ng; g += 256) {
+      const int c = (int)fdiv((uint32_t)g, p.fgp.m, p.fgp.l), q = (g - c * gp) * V;
+      const float* src = p.src + baseP + offP[c] + q;
+      if (V == 4) {
+        const f32x4 v = *reinterpret_cast<const f32x4*>(src);
+#pragma unroll
+        for (int x = 0; x < V; ++x) tile[c * pitch + q + x] = v[x];
+      } else {
+        tile[c * pitch + q] = *src;
+      }
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < n; e += 256) {
-      const int c = e % Bm, q = e / Bm;
-      const int il = q / p.Jl, jl = q - il * p.Jl;
-      p.dst[baseM + c + il * p.sMi + jl * p.sMj] = tile[c * pitch + q];
+    for (int g = threadIdx.x; g < ng; g += 256) {
+      const int q = (int)fdiv((uint32_t)g, p.fgm.m, p.fgm.l), c = (g - q * gm) * V;
+      const int il = (int)fdiv((uint32_t)q, p.fjl.m, p.fjl.l), jl = q - il * p.Jl;
+      const long o = baseM + c + il * p.sMi + jl * p.sMj;
+      float v[V];
+#pragma unroll
+      for (int x = 0; x < V; ++x) v[x] = tile[(c + x) * pitch + q];
+      if (OUT16) {
+        if (V == 4) {
+          uint2 w;
+          w.x = (uint32_t)f32_to_bf16(v[0]) | ((uint32_t)f32_to_bf16(v[1]) << 16);
+          w.y = (uint32_t)f32_to_bf16(v[2]) | ((uint32_t)f32_to_bf16(v[3]) << 16);
+          *reinterpret_cast<uint2*>(p.dst16 + o) = w;
+        } else {
+          p.dst16[o] = f32_to_bf16(v[0]);
+        }
+      } else if (V == 4) {
+        *reinterpret_cast<f32x4*>(p.dst + o) = f32x4{v[0], v[1], v[2], v[3]};
+      } else {
+        p.dst[o] = v[0];
+      }
     }
   } else {
     // matrix -> pair-mode: read runs of Bm, write runs of Bp
-    for (int e = threadIdx.x; e < n; e += 256) {
-      const int c = e % Bm, q = e / Bm;
-      const int il = q / p.Jl, jl = q - il * p.Jl;
-      tile[c * pitch + q] = p.src[baseM + c + il * p.sMi + jl * p.sMj];
+    for (int g = threadIdx.x; g < ng; g += 256) {
+      const int q = (int)fdiv((uint32_t)g, p.fgm.m, p.fgm.l), c = (g - q * gm) * V;
+      const int il = (int)fdiv((uint32_t)q, p.fjl.m, p.fjl.l), jl = q - il * p.Jl;
+      const float* src = p.src + baseM + c + il * p.sMi + jl * p.sMj;
+      if (V == 4) {
+        const f32x4 v = *reinterpret_cast<const f32x4*>(src);
+#pragma unroll
+        for (int x = 0; x < V; ++x) tile[(c + x) * pitch + q] = v[x];
+      } else {
+        tile[c * pitch + q] = *src;
+      }
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < n; e += 256) {
-      const int q = e % Bp, c = e / Bp;
-      p.dst[baseP + offP[c] + q] = tile[c * pitch + q];
+    for (int g = threadIdx.x; g < ng; g += 256) {
+      const int c = (int)fdiv((uint32_t)g, p.fgp.m, p.fgp.l), q = (g - c * gp) * V;
+      float* dst = p.dst + baseP + offP[c] + q;
+      if (V == 4) {
+        *reinterpret_cast<f32x4*>(dst) =
+            f32x4{tile[c * pitch + q], tile[c * pitch + q + 1], tile[c * pitch + q + 2], tile[c * pitch + q + 3]};
+      } else {
+        *dst = tile[c * pitch + q];
+      }
     }
   }
 }
@@ -488,41 +548,68 @@ __global__ __launch_bounds__(256) void mse_final_kernel(const double* partials, 
 }
 
 // ------------------------------------------------------------------ launchers
-template <bool A_KC, bool B_KC, bool BF16>
+template <bool A_KC, bool B_KC, bool BF16, int TM, int TN>
 static hipError_t gemm_launch(const GemmArgs& g, hipStream_t s) {
   constexpr int esz = BF16 ? 2 : 4;
-  const size_t lds = (size_t)4 * tile_elems<BF16>() * esz;
+  const size_t lds = (size_t)2 * (tile_elems<BF16, TM>() + tile_elems<BF16, TN>()) * esz;
   static std::atomic<bool> done[kMaxDevices];
   const hipError_t e = once_per_device(done, [&] {
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm_kernel<A_KC, B_KC, BF16>),
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm_kernel<A_KC, B_KC, BF16, TM, TN>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   });
   if (e != hipSuccess) return e;
-  const int tiles = ((g.M + GBM - 1) / GBM) * ((g.N + GBN - 1) / GBN);
-  hipLaunchKernelGGL((gemm_kernel<A_KC, B_KC, BF16>), dim3(tiles, g.splits), dim3(256), lds, s, g);
+  const int tiles = ((g.M + TM - 1) / TM) * ((g.N + TN - 1) / TN);
+  hipLaunchKernelGGL((gemm_kernel<A_KC, B_KC, BF16, TM, TN>), dim3(tiles, g.splits), dim3(256), lds, s, g);
   return hipGetLastError();
 }
 
+template <bool A_KC, bool B_KC, bool BF16>
+static hipError_t gemm_shape(GemmTile t, const GemmArgs& g, hipStream_t s) {
+  switch (t) {
+    case GEMM_TILE_32x128: return gemm_launch<A_KC, B_KC, BF16, 32, 128>(g, s);
+    case GEMM_TILE_128x32: return gemm_launch<A_KC, B_KC, BF16, 128, 32>(g, s);
+    case GEMM_TILE_128x64: return gemm_launch<A_KC, B_KC, BF16, 128, 64>(g, s);
+    default: return gemm_launch<A_KC, B_KC, BF16, 128, 128>(g, s);
+  }
+}
+
 int gemm_bk(bool bf16) { return bf16 ? GemmCfg<true>::BK : GemmCfg<false>::BK; }
+
+GemmTile gemm_tile(int M, int N) {
+  if (M <= 32 && N > 32) return GEMM_TILE_32x128;
+  if (N <= 32) return GEMM_TILE_128x32;
+  if (N <= 64) return GEMM_TILE_128x64;
+  return GEMM_TILE_128x128;
+}
+
+void gemm_tile_dims(GemmTile t, int* tm, int* tn) {
+  *tm = t == GEMM_TILE_32x128 ? 32 : 128;
+  *tn = t == GEMM_TILE_128x32 ? 32 : (t == GEMM_TILE_128x64 ? 64 : 128);
+}
 
 hipError_t launch_gemm(bool a_kc, bool b_kc, bool bf16, const GemmArgs& g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0) return hipSuccess;
   hipError_t e;
   const int idx = (a_kc ? 4 : 0) + (b_kc ? 2 : 0) + (bf16 ? 1 : 0);
+  const GemmTile t = g.tile;
   switch (idx) {
-    case 0: e = gemm_launch<false, false, false>(g, s); break;
-    case 1: e = gemm_launch<false, false, true>(g, s); break;
-    case 2: e = gemm_launch<false, true, false>(g, s); break;
-    case 3: e = gemm_launch<false, true, true>(g, s); break;
-    case 4: e = gemm_launch<true, false, false>(g, s); break;
-    case 5: e = gemm_launch<true, false, true>(g, s); break;
-    case 6: e = gemm_launch<true, true, false>(g, s); break;
-    default: e = gemm_launch<true, true, true>(g, s); break;
+    case 0: e = gemm_shape<false, false, false>(t, g, s); break;
+    case 1: e = gemm_shape<false, false, true>(t, g, s); break;
+    case 2: e = gemm_shape<false, true, false>(t, g, s); break;
+    case 3: e = gemm_shape<false, true, true>(t, g, s); break;
+    case 4: e = gemm_shape<true, false, false>(t, g, s); break;
+    case 5: e = gemm_shape<true, false, true>(t, g, s); break;
+    case 6: e = gemm_shape<true, true, false>(t, g, s); break;
+    default: e = gemm_shape<true, true, true>(t, g, s); break;
   }
   if (e != hipSuccess || g.splits <= 1) return e;
   const long MN = (long)g.M * g.N;
-  hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)((MN + 31) / 32)), dim3(256), 0, s, g.slab, g.splits,
-                     g.M, g.N, g.alpha, g.C, g.ldc);
+  if (g.splits >= 256 && MN <= 65536)
+    hipLaunchKernelGGL(splitk_reduce_kernel<64>, dim3((unsigned)((MN + 3) / 4)), dim3(256), 0, s, g.slab, g.splits,
+                       g.M, g.N, g.alpha, g.C, g.ldc);
+  else
+    hipLaunchKernelGGL(splitk_reduce_kernel<8>, dim3((unsigned)((MN + 31) / 32)), dim3(256), 0, s, g.slab,
+                       g.splits, g.M, g.N, g.alpha, g.C, g.ldc);
   return hipGetLastError();
 }
 
@@ -544,9 +631,23 @@ hipError_t launch_core_perm(const float* src, float* dst, int R, int I, int J, i
   return hipGetLastError();
 }
 
-hipError_t launch_tile_permute(const TilePermArgs& p, hipStream_t s) {
-  if (p.tiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(tile_permute_kernel, dim3((unsigned)p.tiles), dim3(256), 0, s, p);
+hipError_t launch_tile_permute(const TilePermArgs& in, hipStream_t s) {
+  if (in.tiles <= 0) return hipSuccess;
+  TilePermArgs p = in;
+  const int v = p.vec ? 4 : 1;
+  p.fgp = make_fastdiv((uint32_t)(p.Bp / v));
+  p.fgm = make_fastdiv((uint32_t)(p.Bm / v));
+  p.fjl = make_fastdiv((uint32_t)p.Jl);
+  const bool o16 = p.dir == 0 && p.dst16;
+  const dim3 grid((unsigned)p.tiles);
+  if (p.vec && o16)
+    hipLaunchKernelGGL((tile_permute_kernel<4, true>), grid, dim3(256), 0, s, p);
+  else if (p.vec)
+    hipLaunchKernelGGL((tile_permute_kernel<4, false>), grid, dim3(256), 0, s, p);
+  else if (o16)
+    hipLaunchKernelGGL((tile_permute_kernel<1, true>), grid, dim3(256), 0, s, p);
+  else
+    hipLaunchKernelGGL((tile_permute_kernel<1, false>), grid, dim3(256), 0, s, p);
   return hipGetLastError();
 }
 

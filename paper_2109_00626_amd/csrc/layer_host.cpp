@@ -177,13 +177,18 @@ ttc_status gemm(bool a_kc, const float* A, long lda, bool b_kc, const float* B, 
   g.alpha = 1.f;
   g.vec_a = (lda % 4 == 0) && aligned16(A);
   g.vec_b = (ldb % 4 == 0) && aligned16(B);
-  const long tiles = (long)((M + 127) / 128) * ((N + 127) / 128);
+  g.tile = gemm_tile(M, N);
+  int tm = 128, tn = 128;
+  gemm_tile_dims(g.tile, &tm, &tn);
+  const long tiles = (long)((M + tm - 1) / tm) * ((N + tn - 1) / tn);
   const int bk = gemm_bk(bf16);
   int splits = 1;
   if (tiles < 512 && !map) {
-    // about 1024 workgroups, at most 256 partial slabs (the reduction reads
-    // every slab once per output element)
-    long want = std::min(256L, (1024 + tiles - 1) / tiles);
+    // about 1024 workgroups; at most 256 partial slabs (the reduction reads
+    // every slab once per output element), 1024 for outputs of at most 64 K
+    // elements
+    const long cap = (long)M * N <= 65536 ? 1024L : 256L;
+    long want = std::min(cap, (1024 + tiles - 1) / tiles);
     long by_k = K / (4L * bk);
     long by_slab = (long)(kSlabElems / ((size_t)M * N));
     splits = (int)std::max(1L, std::min(want, std::min(by_k, by_slab)));
@@ -195,9 +200,13 @@ ttc_status gemm(bool a_kc, const float* A, long lda, bool b_kc, const float* B, 
 }
 
 // The pair-mode <-> matrix permutation of an MPO's dense matrix: the tiled
-// kernel when a tile of at least two leading column digits fits in LDS,
-// else one thread per element.
-ttc_status permute_dense(const ttc_ttm* m, int dir, long cols, const float* src, float* dst, hipStream_t s) {
+// kernel when a tile of at least two leading matrix digits fits in LDS,
+// else one thread per element.  trans: the matrix is W^T (cols x rows);
+// dst16 (dir 0): written as BF16.  The per-element kernel serves only the
+// FP32 untransposed form: *done is false when it would be needed for the
+// others.
+ttc_status permute_dense(const ttc_ttm* m, int dir, const float* src, float* dst, hipStream_t s,
+                         bool trans = false, uint16_t* dst16 = nullptr, bool* done = nullptr) {
   const int d = m->order;
   std::vector<long> pstride(d), ri(d), cj(d);
   pstride[d - 1] = 1;
@@ -207,13 +216,29 @@ ttc_status permute_dense(const ttc_ttm* m, int dir, long cols, const float* src,
     ri[k] = ri[k - 1] * m->rows[k - 1];
     cj[k] = cj[k - 1] * m->cols[k - 1];
   }
-  long total = 1;
-  for (int k = 0; k < d; ++k) total *= (long)m->rows[k] * m->cols[k];
+  const long rows = ri[d - 1] * m->rows[d - 1], cols = cj[d - 1] * m->cols[d - 1];
+  // matrix strides of the digits i_k and j_k; pair-mode strides
+  std::vector<long> si(d), sj(d), pi(d), pj(d);
+  for (int k = 0; k < d; ++k) {
+    si[k] = trans ? ri[k] : ri[k] * cols;
+    sj[k] = trans ? cj[k] * rows : cj[k];
+    pi[k] = (long)m->cols[k] * pstride[k];
+    pj[k] = pstride[k];
+  }
+  // the matrix's contiguous digits: j_0, j_1, .. (W) or i_0, i_1, .. (W^T)
+  const int* lrad = trans ? m->rows : m->cols;
+  const std::vector<long>& lP = trans ? pi : pj;
+  const std::vector<long>& lM = trans ? si : sj;
+  const int* orad_other = trans ? m->cols : m->rows;
+  const std::vector<long>& oP = trans ? pj : pi;
+  const std::vector<long>& oM = trans ? sj : si;
+  long total = rows * cols;
+  if (done) *done = true;
   if (d >= 2) {
     const int Bp = m->rows[d - 1] * m->cols[d - 1];
     int t = 0, Bm = 1;
-    while (t < d - 1 && (long)Bm * m->cols[t] <= 256 && (long)Bm * m->cols[t] * (Bp + 1) <= kTilePermElems + 64) {
-      Bm *= m->cols[t];
+    while (t < d - 1 && (long)Bm * lrad[t] <= 256 && (long)Bm * lrad[t] * (Bp + 1) <= kTilePermElems + 64) {
+      Bm *= lrad[t];
       ++t;
     }
     if (Bm >= 2) {
@@ -222,33 +247,40 @@ ttc_status permute_dense(const ttc_ttm* m, int dir, long cols, const float* src,
       tp.dir = dir;
       tp.Bp = Bp;
       tp.Jl = m->cols[d - 1];
-      tp.sMi = ri[d - 1] * cols;
-      tp.sMj = cj[d - 1];
+      tp.sMi = si[d - 1];
+      tp.sMj = sj[d - 1];
       tp.t = t;
       tp.Bm = Bm;
       for (int k = 0; k < t; ++k) {
-        tp.jrad[k] = m->cols[k];
-        tp.sPj[k] = pstride[k];
+        tp.jrad[k] = lrad[k];
+        tp.sPj[k] = lP[k];
       }
-      // outer digits, the matrix's faster ones first: j_t .. j_{d-2}, i_0 .. i_{d-2}
+      // outer digits, the matrix's faster ones first
       int q = 0;
       for (int k = t; k < d - 1; ++k, ++q) {
-        tp.orad[q] = m->cols[k];
-        tp.osP[q] = pstride[k];
-        tp.osM[q] = cj[k];
+        tp.orad[q] = lrad[k];
+        tp.osP[q] = lP[k];
+        tp.osM[q] = lM[k];
       }
       for (int k = 0; k < d - 1; ++k, ++q) {
-        tp.orad[q] = m->rows[k];
-        tp.osP[q] = (long)m->cols[k] * pstride[k];
-        tp.osM[q] = ri[k] * cols;
+        tp.orad[q] = orad_other[k];
+        tp.osP[q] = oP[k];
+        tp.osM[q] = oM[k];
       }
       tp.nout = q;
       tp.tiles = total / ((long)Bp * Bm);
       tp.src = src;
       tp.dst = dst;
+      tp.dst16 = dir == 0 ? dst16 : nullptr;
+      const uintptr_t al = (uintptr_t)src | (dst16 ? 0 : (uintptr_t)dst);
+      tp.vec = Bp % 4 == 0 && Bm % 4 == 0 && (al & 15) == 0 && ((uintptr_t)dst16 & 7) == 0;
       TTC_HIP(launch_tile_permute(tp, s));
       return TTC_OK;
     }
+  }
+  if (trans || dst16) {
+    if (done) *done = false;
+    return TTC_OK;
   }
   PermArgs pa;
   std::memset(&pa, 0, sizeof(pa));
@@ -267,9 +299,9 @@ ttc_status permute_dense(const ttc_ttm* m, int dir, long cols, const float* src,
   return TTC_OK;
 }
 
-// Dense matrix W[i, j] from the cores: chain L_{k+1} = L_k . W^(k), then the
-// pair-mode -> matrix permutation.  Keeps every L_k in the plan.
-ttc_status build_dense(const ttc_ttm* m, LayerPlan& p, hipStream_t s) {
+// The chain L_{k+1} = L_k . W^(k) (pair-mode order in Dp).  Keeps every L_k
+// in the plan.
+ttc_status build_chain(const ttc_ttm* m, LayerPlan& p, hipStream_t s) {
   const int d = m->order;
   const float* cur = reinterpret_cast<const float*>(m->cores[0]);  // L_1: |m_<1| x R_1
   for (int k = 1; k < d; ++k) {
@@ -280,7 +312,34 @@ ttc_status build_dense(const ttc_ttm* m, LayerPlan& p, hipStream_t s) {
                  (int)p.mprefix[k], (int)(Mk * R1), R, false, p.slab, s));
     cur = out;
   }
-  return permute_dense(m, 0, p.cols, d == 1 ? reinterpret_cast<const float*>(m->cores[0]) : p.Dp, p.Wd, s);
+  return TTC_OK;
+}
+
+const float* pair_order(const ttc_ttm* m, const LayerPlan& p) {
+  return m->order == 1 ? reinterpret_cast<const float*>(m->cores[0]) : p.Dp;
+}
+
+// Dense matrix W[i, j] (FP32, in p.Wd) from the cores: the chain, then the
+// pair-mode -> matrix permutation.
+ttc_status build_dense(const ttc_ttm* m, LayerPlan& p, hipStream_t s) {
+  TTC_TRY(build_chain(m, p, s));
+  return permute_dense(m, 0, pair_order(m, p), p.Wd, s);
+}
+
+// The BF16 operand of a product with W into p.B16: W (k = j contiguous) or,
+// trans, W^T (k = i contiguous), written by the permutation itself when the
+// tiled form applies, else through the FP32 matrix and a conversion pass.
+ttc_status build_dense16(const ttc_ttm* m, LayerPlan& p, bool trans, hipStream_t s) {
+  TTC_TRY(build_chain(m, p, s));
+  bool done = false;
+  TTC_TRY(permute_dense(m, 0, pair_order(m, p), p.Wd, s, trans, p.B16, &done));
+  if (done) return TTC_OK;
+  TTC_TRY(permute_dense(m, 0, pair_order(m, p), p.Wd, s));
+  if (trans)
+    TTC_HIP(launch_cvt16_t(p.Wd, p.B16, p.rows, p.cols, s));
+  else
+    TTC_HIP(launch_cvt16(p.Wd, p.B16, p.rows * p.cols, s));
+  return TTC_OK;
 }
 
 // ------------------------------------------------- core-by-core schedule
@@ -291,8 +350,7 @@ struct CoresPlan {
   std::vector<long> P, Q, K, N;  // per step
   std::vector<float*> Wp;        // permuted cores
   std::vector<float*> Z;         // Z_k, k = 1..d-1
-  float* dC = nullptr;           // backward buffers
-  float* dZ = nullptr;
+  float* dC[2] = {nullptr, nullptr};  // backward: output gradients of two steps
   float* dWp = nullptr;
   float* slab = nullptr;
 };
@@ -344,10 +402,12 @@ void plan_cores(const ttc_ttm* m, long batch, bool backward, Arena& a, CoresPlan
     cmax = std::max(cmax, p->P[k] * p->Q[k] * p->N[k]);
     wmax = std::max(wmax, p->K[k] * p->N[k]);
   }
+  (void)zmax;
   if (backward) {
+    // every Z_k kept (the backward reads them), then the gradient buffers
     for (int k = 1; k < d; ++k) p->Z[k] = a.take((size_t)p->P[k] * p->Q[k] * p->K[k]);
-    p->dC = a.take((size_t)cmax);
-    p->dZ = a.take((size_t)zmax);
+    p->dC[0] = a.take((size_t)cmax);
+    p->dC[1] = d > 1 ? a.take((size_t)cmax) : nullptr;
     p->dWp = a.take((size_t)wmax);
   } else if (d > 1) {
     float* buf[2] = {a.take((size_t)zmax), d > 2 ? a.take((size_t)zmax) : nullptr};
@@ -373,6 +433,24 @@ IdxMap step_map(const ttc_ttm* m, const CoresPlan& p, int k) {
   return mp;
 }
 
+// The inverse of step k's store map as the store map of the product that
+// yields the gradient of Z_{k+1} (rows (p', i_k, q), columns (j_{k+1},
+// r_{k+1})): it writes the gradient of step k's output straight into that
+// output's own layout [(p', j_{k+1}, q), (i_k, r_{k+1})].
+IdxMap step_map_inv(const ttc_ttm* m, const CoresPlan& p, int k) {
+  const long Jn = m->cols[k + 1], Rn = m->ranks[k + 1], Q = p.Q[k], I = m->rows[k];
+  IdxMap mp;
+  mp.mr0 = (int)Q;
+  mp.mr1 = (int)I;
+  mp.ms0 = I * Rn;
+  mp.ms1 = Rn;
+  mp.ms2 = Jn * Q * I * Rn;
+  mp.nr0 = (int)Rn;
+  mp.ns0 = 1;
+  mp.ns1 = Q * I * Rn;
+  return mp;
+}
+
 // Forward steps; with Y null the last step is skipped (backward recompute).
 ttc_status cores_forward(const ttc_ttm* m, const CoresPlan& p, const float* X, float* Y, bool bf16, hipStream_t s) {
   const int d = p.d;
@@ -391,49 +469,60 @@ ttc_status cores_forward(const ttc_ttm* m, const CoresPlan& p, const float* X, f
   return TTC_OK;
 }
 
+// saved: Z_k and Wp_k are in the workspace from the forward (schedule
+// CORES_SAVED), else they are recomputed.  The gradient of the last step's
+// output is gathered from dY; every other step's comes from the product
+// dZ_{k+1} = dC_{k+1} Wp_{k+1}^T, stored through the inverse map straight
+// into the layout of dC_k.
 ttc_status cores_backward(const ttc_ttm* m, const CoresPlan& p, const float* X, const float* dY, float* dX,
-                          void* const* dcores, bool bf16, hipStream_t s) {
+                          void* const* dcores, bool bf16, bool saved, hipStream_t s) {
   const int d = p.d;
-  TTC_TRY(cores_forward(m, p, X, nullptr, bf16, s));
-  const float* g = dY;  // gradient of step k's output, in its stored layout
+  if (!saved) TTC_TRY(cores_forward(m, p, X, nullptr, bf16, s));
+  {
+    GatherArgs ga;
+    ga.M = p.P[d - 1] * p.Q[d - 1];
+    ga.N = p.N[d - 1];
+    ga.map = step_map(m, p, d - 1);
+    ga.src = dY;
+    ga.dst = p.dC[(d - 1) & 1];
+    TTC_HIP(launch_gather(ga, s));
+  }
   for (int k = d - 1; k >= 0; --k) {
     const long M = p.P[k] * p.Q[k];
-    GatherArgs ga;
-    ga.M = M;
-    ga.N = p.N[k];
-    ga.map = step_map(m, p, k);
-    ga.src = g;
-    ga.dst = p.dC;
-    TTC_HIP(launch_gather(ga, s));
+    const float* dC = p.dC[k & 1];
     if (dcores) {
       // dWp_k = Z_k^T dC_k: A(m = (j, r), k = row) = Z_k[row * K + m], B(k = row, n) = dC[row * N + n]
       const float* Zk = k == 0 ? X : p.Z[k];
-      TTC_TRY(gemm(false, Zk, p.K[k], false, p.dC, p.N[k], p.dWp, p.N[k], (int)p.K[k], (int)p.N[k], (int)M, bf16,
+      TTC_TRY(gemm(false, Zk, p.K[k], false, dC, p.N[k], p.dWp, p.N[k], (int)p.K[k], (int)p.N[k], (int)M, bf16,
                    p.slab, s));
       TTC_HIP(launch_core_perm(p.dWp, reinterpret_cast<float*>(dcores[k]), m->ranks[k], m->rows[k], m->cols[k],
                                m->ranks[k + 1], 1, s));
     }
-    float* out = k > 0 ? p.dZ : dX;
-    if (out) {
-      // dZ_k = dC_k Wp_k^T: B(k = n_fwd, n = (j, r)) = Wp_k[(j, r) * N + n_fwd]
-      TTC_TRY(gemm(true, p.dC, p.N[k], true, p.Wp[k], p.N[k], out, p.K[k], (int)M, (int)p.K[k], (int)p.N[k], bf16,
+    // dZ_k = dC_k Wp_k^T: B(k = n_fwd, n = (j, r)) = Wp_k[(j, r) * N + n_fwd]
+    if (k > 0) {
+      const IdxMap mp = step_map_inv(m, p, k - 1);
+      TTC_TRY(gemm(true, dC, p.N[k], true, p.Wp[k], p.N[k], p.dC[(k - 1) & 1], 0, (int)M, (int)p.K[k],
+                   (int)p.N[k], bf16, p.slab, s, &mp));
+    } else if (dX) {
+      TTC_TRY(gemm(true, dC, p.N[k], true, p.Wp[k], p.N[k], dX, p.K[k], (int)M, (int)p.K[k], (int)p.N[k], bf16,
                    p.slab, s));
     }
-    g = p.dZ;
   }
   return TTC_OK;
 }
 
 // Validates the call and resolves the schedule (AUTO: fewer FLOPs).
 ttc_status check_common(const ttc_ttm* m, int64_t batch, ttc_prec prec, ttc_sched sched, bool* bf16,
-                        bool* cores) {
+                        bool* cores, bool* saved = nullptr) {
   TTC_TRY(check_ttm(m));
   if (batch < 1 || batch > 2147483647LL) return fail(TTC_ERR_SHAPE, "batch outside [1, 2^31)");
   if (prec == TTC_PREC_BF16) *bf16 = true;
   else if (prec == TTC_PREC_AUTO || prec == TTC_PREC_F32) *bf16 = false;
   else return fail(TTC_ERR_UNSUPPORTED, "TT layer precision must be AUTO, F32 or BF16");
-  if (sched != TTC_SCHED_AUTO && sched != TTC_SCHED_DENSE && sched != TTC_SCHED_CORES)
+  if (sched != TTC_SCHED_AUTO && sched != TTC_SCHED_DENSE && sched != TTC_SCHED_CORES &&
+      sched != TTC_SCHED_CORES_SAVED)
     return fail(TTC_ERR_UNSUPPORTED, "unknown schedule");
+  if (saved) *saved = sched == TTC_SCHED_CORES_SAVED;
   CoresPlan cp;
   cores_shape(m, (long)batch, &cp);
   bool cores_ok = true;
@@ -441,9 +530,9 @@ ttc_status check_common(const ttc_ttm* m, int64_t batch, ttc_prec prec, ttc_sche
     if ((double)cp.P[k] * cp.Q[k] * std::max(cp.K[k], cp.N[k]) >= 9.2e18 / 8 ||
         (double)cp.P[k] * cp.Q[k] >= 2147483647.0)
       cores_ok = false;
-  if (sched == TTC_SCHED_CORES && !cores_ok)
+  if ((sched == TTC_SCHED_CORES || sched == TTC_SCHED_CORES_SAVED) && !cores_ok)
     return fail(TTC_ERR_SHAPE, "core-by-core intermediates exceed 2^31 rows");
-  *cores = sched == TTC_SCHED_CORES ||
+  *cores = sched == TTC_SCHED_CORES || sched == TTC_SCHED_CORES_SAVED ||
            (sched == TTC_SCHED_AUTO && cores_ok && cores_flops(cp) < dense_flops(m, (long)batch));
   return TTC_OK;
 }
@@ -454,13 +543,13 @@ extern "C" {
 
 ttc_status ttm_apply_dense_query(const ttc_ttm* m, int64_t batch, ttc_prec prec, ttc_sched sched, int32_t backward,
                                  size_t* ws_bytes) {
-  bool bf16 = false, cores = false;
-  TTC_TRY(check_common(m, batch, prec, sched, &bf16, &cores));
+  bool bf16 = false, cores = false, saved = false;
+  TTC_TRY(check_common(m, batch, prec, sched, &bf16, &cores, &saved));
   if (!ws_bytes) return fail(TTC_ERR_NULL, "ws_bytes is NULL");
   Arena a(nullptr);
   if (cores) {
     CoresPlan p;
-    plan_cores(m, (long)batch, backward != 0, a, &p);
+    plan_cores(m, (long)batch, backward != 0 || saved, a, &p);
   } else {
     LayerPlan p;
     plan_layer(m, backward != 0, bf16, (long)batch, a, &p);
@@ -476,25 +565,26 @@ ttc_status ttm_apply_dense(const ttc_ttm* m, const void* d_x, int64_t batch, voi
   if (!d_x || !d_y) return fail(TTC_ERR_NULL, "d_x or d_y is NULL");
   if (need > ws_bytes) return fail(TTC_ERR_WORKSPACE, "workspace smaller than ttm_apply_dense_query size");
   if (!d_ws) return fail(TTC_ERR_NULL, "d_ws is NULL");
-  bool bf16 = false, cores = false;
-  TTC_TRY(check_common(m, batch, prec, sched, &bf16, &cores));
+  bool bf16 = false, cores = false, saved = false;
+  TTC_TRY(check_common(m, batch, prec, sched, &bf16, &cores, &saved));
   hipStream_t s = (hipStream_t)stream;
   Arena a(d_ws);
   if (cores) {
+    // saved: the backward's layout, every Z_k kept
     CoresPlan p;
-    plan_cores(m, (long)batch, false, a, &p);
+    plan_cores(m, (long)batch, saved, a, &p);
     return cores_forward(m, p, reinterpret_cast<const float*>(d_x), reinterpret_cast<float*>(d_y), bf16, s);
   }
   LayerPlan p;
   plan_layer(m, false, bf16, (long)batch, a, &p);
-  TTC_TRY(build_dense(m, p, s));
   const float* X = reinterpret_cast<const float*>(d_x);
   if (bf16 && use_gemm16(batch, p.rows, p.cols) && aligned16(X)) {
+    TTC_TRY(build_dense16(m, p, false, s));
     TTC_HIP(launch_cvt16(X, p.A16, (long)batch * p.cols, s));
-    TTC_HIP(launch_cvt16(p.Wd, p.B16, p.rows * p.cols, s));
     return gemm16(p.A16, p.cols, p.B16, p.cols, reinterpret_cast<float*>(d_y), p.rows, (int)batch, (int)p.rows,
                   (int)p.cols, s);
   }
+  TTC_TRY(build_dense(m, p, s));
   // Y = X . W^T: A = X (batch x cols), B(k = j, n = i) = W[i * cols + j]
   return gemm(true, reinterpret_cast<const float*>(d_x), p.cols, true, p.Wd, p.cols, reinterpret_cast<float*>(d_y),
               p.rows, (int)batch, (int)p.rows, (int)p.cols, bf16, p.slab, s);
@@ -512,24 +602,27 @@ ttc_status ttm_apply_dense_bwd(const ttc_ttm* m, const void* d_x, const void* d_
   if (d_dcores)
     for (int k = 0; k < d; ++k)
       if (!d_dcores[k]) return fail(TTC_ERR_NULL, "NULL core-gradient buffer");
-  bool bf16 = false, cores = false;
-  TTC_TRY(check_common(m, batch, prec, sched, &bf16, &cores));
+  bool bf16 = false, cores = false, saved = false;
+  TTC_TRY(check_common(m, batch, prec, sched, &bf16, &cores, &saved));
   hipStream_t s = (hipStream_t)stream;
   Arena a(d_ws);
   if (cores) {
     CoresPlan p;
     plan_cores(m, (long)batch, true, a, &p);
     return cores_backward(m, p, reinterpret_cast<const float*>(d_x), reinterpret_cast<const float*>(d_dy),
-                          reinterpret_cast<float*>(d_dx), d_dcores, bf16, s);
+                          reinterpret_cast<float*>(d_dx), d_dcores, bf16, saved, s);
   }
   LayerPlan p;
   plan_layer(m, true, bf16, (long)batch, a, &p);
-  TTC_TRY(build_dense(m, p, s));
   const float* X = reinterpret_cast<const float*>(d_x);
   const float* dY = reinterpret_cast<const float*>(d_dy);
   const bool al = aligned16(X) && aligned16(dY);
   const bool dx16 = d_dx && bf16 && al && use_gemm16(batch, p.cols, p.rows);
   const bool dw16 = d_dcores && bf16 && al && use_gemm16(p.rows, p.cols, batch);
+  if (dx16)
+    TTC_TRY(build_dense16(m, p, true, s));  // W^T in BF16
+  else
+    TTC_TRY(build_dense(m, p, s));
   if (dx16 && dw16) {
     // dY in both layouts from one read
     TTC_HIP(launch_cvt16_both(dY, p.A16, p.C16, batch, p.rows, s));
@@ -538,7 +631,6 @@ ttc_status ttm_apply_dense_bwd(const ttc_ttm* m, const void* d_x, const void* d_
   }
   if (dx16) {
     // dX = dY . W: A = dY (batch x rows, k = i), B = W^T (cols x rows, k = i)
-    TTC_HIP(launch_cvt16_t(p.Wd, p.B16, p.rows, p.cols, s));
     TTC_TRY(gemm16(p.A16, p.rows, p.B16, p.rows, reinterpret_cast<float*>(d_dx), p.cols, (int)batch, (int)p.cols,
                    (int)p.rows, s));
   } else if (d_dx) {
@@ -557,7 +649,7 @@ ttc_status ttm_apply_dense_bwd(const ttc_ttm* m, const void* d_x, const void* d_
                  p.slab, s));
   }
   // dW -> pair-mode order (the right environment of the last core)
-  TTC_TRY(permute_dense(m, 1, p.cols, p.Wd, d == 1 ? reinterpret_cast<float*>(d_dcores[0]) : p.Dp, s));
+  TTC_TRY(permute_dense(m, 1, p.Wd, d == 1 ? reinterpret_cast<float*>(d_dcores[0]) : p.Dp, s));
   const float* Rt = p.Dp;  // Rt_{d-1}: |m_<d-1| x (M_{d-1} R_d)
   for (int k = d - 1; k >= 1; --k) {
     const long Mk = (long)m->rows[k] * m->cols[k];

@@ -5,10 +5,10 @@
 // free core next to it and its column index q is carried through the other
 // side's cores as an extra bond factor (merged index (own bond) * Q + q).
 // The carried-bond cores are block-diagonal copies: almost all of their
-// entries are zero, so the kernel is a pure HBM write stream.  Work is split
-// into lines (one fixed row bond and mode index, d1 contiguous outputs);
-// each thread writes 4 consecutive outputs with one 16-byte store, the
-// block-diagonal cores without a division per output.
+// entries are zero, so the kernel is a pure HBM write stream: the cores
+// are written as one stream of 16-byte runs (consecutive outputs of one row
+// bond and mode index), the block-diagonal ones with at most one source
+// load per run.
 //
 // Dense form (small cases): every output entry is the product of the core
 // slices along its multi-index (eq. (9)).
@@ -60,54 +60,88 @@ __device__ __forceinline__ Tc lift_value(const LiftCore& c, const Tc* K, int Q, 
   }
 }
 
-// One line (one row bond and mode index: d1 consecutive outputs) of core cc.
-template <typename Tin, typename Tc>
-__device__ __forceinline__ void lift_line(const LiftArgs& a, const LiftCore& c, int l) {
-  const int row = l / c.n, i = l - row * c.n;
-  const Tc* K = reinterpret_cast<const Tc*>(a.K);
-  Tc* dst = reinterpret_cast<Tc*>(c.dst) + (long)l * c.d1;
-  const int d1 = c.d1;
-  if (sizeof(Tc) == 4 && (d1 & 3) == 0 && c.op == LIFT_DELTA && (a.Q & 3) == 0) {
-    // block-diagonal copy: in line (row, i) only the columns b*Q + q hold
-    // entries (row = a*Q + q); the four columns of a thread share b, so one
-    // division per four outputs and at most one load
-    const int ra = row / a.Q, q = row - ra * a.Q;
-    const Tin* src = reinterpret_cast<const Tin*>(c.src) + ((long)ra * c.n + i) * c.r1;
-    for (int j = 4 * threadIdx.x; j < d1; j += 4 * blockDim.x) {
-      const int b = j / a.Q, u = q - (j - b * a.Q);
-      f32x4 v = {0.f, 0.f, 0.f, 0.f};
-      if (u >= 0 && u < 4) {
-        const float e = (float)cvt<Tc>(src[b]);
-        v[0] = u == 0 ? e : 0.f;
-        v[1] = u == 1 ? e : 0.f;
-        v[2] = u == 2 ? e : 0.f;
-        v[3] = u == 3 ? e : 0.f;
-      }
-      __builtin_nontemporal_store(v, reinterpret_cast<f32x4*>(dst + j));
-    }
-  } else if (sizeof(Tc) == 4 && (d1 & 3) == 0) {
-    for (int j = 4 * threadIdx.x; j < d1; j += 4 * blockDim.x) {
-      f32x4 v;
-      v[0] = (float)lift_value<Tin, Tc>(c, K, a.Q, row, i, j);
-      v[1] = (float)lift_value<Tin, Tc>(c, K, a.Q, row, i, j + 1);
-      v[2] = (float)lift_value<Tin, Tc>(c, K, a.Q, row, i, j + 2);
-      v[3] = (float)lift_value<Tin, Tc>(c, K, a.Q, row, i, j + 3);
-      __builtin_nontemporal_store(v, reinterpret_cast<f32x4*>(dst + j));
-    }
-  } else {
-    for (int j = threadIdx.x; j < d1; j += blockDim.x) dst[j] = lift_value<Tin, Tc>(c, K, a.Q, row, i, j);
-  }
-}
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<float> {
+  typedef float type __attribute__((ext_vector_type(4)));
+};
+template <>
+struct Vec16<double> {
+  typedef double type __attribute__((ext_vector_type(2)));
+};
 
-// Workgroups walk the lines of every output core in a grid-stride loop (a
-// few thousand workgroups, each writing many lines, rather than one
-// workgroup per line).
+constexpr int kLiftUnroll = 4;
+
+// The output cores as one stream of items (a run of `vec` consecutive
+// outputs of one line; 16 bytes when the line length allows).  A thread
+// takes kLiftUnroll items a grid stride apart and computes all of them
+// (issuing their source loads together) before it stores any, so one
+// load latency covers several stores.  Item ranges start at multiples of
+// 64, so a wave's items lie in one core and the core lookup is uniform.
 template <typename Tin, typename Tc>
-__global__ __launch_bounds__(256) void lift_kernel(LiftArgs a, int total_lines) {
-  int cc = 0;
-  for (int L = blockIdx.x; L < total_lines; L += gridDim.x) {
-    while (cc + 1 < a.ncores && a.c[cc + 1].line_begin <= L) ++cc;
-    lift_line<Tin, Tc>(a, a.c[cc], L - a.c[cc].line_begin);
+__global__ __launch_bounds__(256) void lift_kernel(LiftArgs a, long total_items) {
+  constexpr int VW = 16 / sizeof(Tc);
+  typedef typename Vec16<Tc>::type vec_t;
+  const Tc* K = reinterpret_cast<const Tc*>(a.K);
+  const long stride = (long)gridDim.x * blockDim.x;
+  const int lane = threadIdx.x & 63;
+  int cc[kLiftUnroll];
+#pragma unroll
+  for (int u = 0; u < kLiftUnroll; ++u) cc[u] = 0;
+  for (long w0 = (long)blockIdx.x * blockDim.x + (threadIdx.x & ~63); w0 < total_items;
+       w0 += kLiftUnroll * stride) {
+    vec_t v[kLiftUnroll];
+    Tc* p[kLiftUnroll];
+#pragma unroll
+    for (int u = 0; u < kLiftUnroll; ++u) {
+      p[u] = nullptr;
+      const long ew = w0 + u * stride;  // the wave's first item
+      if (ew >= total_items) continue;
+      int k = cc[u];
+      while (k + 1 < a.ncores && a.c[k + 1].item_begin <= ew) ++k;
+      k = __builtin_amdgcn_readfirstlane(k);
+      cc[u] = k;
+      const LiftCore& c = a.c[k];
+      const long t = ew + lane - c.item_begin;
+      if (t >= c.items) continue;
+      long l;
+      int j;
+      if (c.items <= 0xffffffffL) {
+        const uint32_t ll = fdiv((uint32_t)t, c.fw.m, c.fw.l);
+        l = ll;
+        j = ((int)((uint32_t)t - ll * (uint32_t)c.w)) * c.vec;
+      } else {
+        l = t / c.w;
+        j = (int)(t - l * c.w) * c.vec;
+      }
+      const int row = (int)fdiv((uint32_t)l, c.fn.m, c.fn.l), i = (int)l - row * c.n;
+      p[u] = reinterpret_cast<Tc*>(c.dst) + l * c.d1 + j;
+      if (c.vec == 1) {
+        v[u][0] = lift_value<Tin, Tc>(c, K, a.Q, row, i, j);
+      } else if (c.op == LIFT_DELTA && a.Q % VW == 0) {
+        // block-diagonal copy: line (row = ra * Q + q, i) holds entries only
+        // at the columns b * Q + q, so this run holds at most one (at slot
+        // s) and needs at most one load
+        const int ra = (int)fdiv((uint32_t)row, a.fq.m, a.fq.l), q = row - ra * a.Q;
+        const int b = (int)fdiv((uint32_t)j, a.fq.m, a.fq.l), sl = q - (j - b * a.Q);
+        Tc e = (Tc)0;
+        if (sl >= 0 && sl < VW) e = cvt<Tc>(reinterpret_cast<const Tin*>(c.src)[((long)ra * c.n + i) * c.r1 + b]);
+#pragma unroll
+        for (int x = 0; x < VW; ++x) v[u][x] = x == sl ? e : (Tc)0;
+      } else {
+#pragma unroll
+        for (int x = 0; x < VW; ++x) v[u][x] = lift_value<Tin, Tc>(c, K, a.Q, row, i, j + x);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kLiftUnroll; ++u) {
+      if (!p[u]) continue;
+      if (a.c[cc[u]].vec == 1)
+        *p[u] = v[u][0];
+      else
+        __builtin_nontemporal_store(v[u], reinterpret_cast<vec_t*>(p[u]));
+    }
   }
 }
 
@@ -138,16 +172,32 @@ __global__ __launch_bounds__(256) void dense_kernel(DenseArgs a) {
   reinterpret_cast<Tc*>(a.out)[e] = v[0];
 }
 
-// Workgroups of the lift: eight per compute unit.
-const int kLiftGrid = 2048;
+// Workgroups of the lift at most (a grid-stride loop covers the rest).
+const long kLiftGrid = 8192;
 
-hipError_t launch_lift(ttc_dtype dt, const LiftArgs& a, int total_lines, hipStream_t s) {
+hipError_t launch_lift(ttc_dtype dt, const LiftArgs& in, int total_lines, hipStream_t s) {
   if (total_lines <= 0) return hipSuccess;
-  const int grid = std::min(total_lines, kLiftGrid);
+  LiftArgs a = in;
+  const int VW = dt == TTC_F64 ? 2 : 4;
+  a.fq = make_fastdiv((uint32_t)std::max(a.Q, 1));
+  long items = 0;
+  for (int k = 0; k < a.ncores; ++k) {
+    LiftCore& c = a.c[k];
+    const bool v = c.d1 % VW == 0 && ((uintptr_t)c.dst & 15) == 0;
+    c.vec = v ? VW : 1;
+    c.w = c.d1 / c.vec;
+    c.items = (long)c.d0 * c.n * c.w;
+    c.item_begin = items;
+    c.fw = make_fastdiv((uint32_t)std::max(c.w, 1));
+    c.fn = make_fastdiv((uint32_t)std::max(c.n, 1));
+    items += (c.items + 63) / 64 * 64;
+  }
+  if (items <= 0) return hipSuccess;
+  const int grid = (int)std::min((items + 256L * kLiftUnroll - 1) / (256L * kLiftUnroll), kLiftGrid);
   switch (dt) {
-    case TTC_F64: hipLaunchKernelGGL((lift_kernel<double, double>), dim3(grid), dim3(256), 0, s, a, total_lines); break;
-    case TTC_F32: hipLaunchKernelGGL((lift_kernel<float, float>), dim3(grid), dim3(256), 0, s, a, total_lines); break;
-    default: hipLaunchKernelGGL((lift_kernel<bf16_t, float>), dim3(grid), dim3(256), 0, s, a, total_lines); break;
+    case TTC_F64: hipLaunchKernelGGL((lift_kernel<double, double>), dim3(grid), dim3(256), 0, s, a, items); break;
+    case TTC_F32: hipLaunchKernelGGL((lift_kernel<float, float>), dim3(grid), dim3(256), 0, s, a, items); break;
+    default: hipLaunchKernelGGL((lift_kernel<bf16_t, float>), dim3(grid), dim3(256), 0, s, a, items); break;
   }
   return hipGetLastError();
 }

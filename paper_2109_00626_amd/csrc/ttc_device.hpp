@@ -25,6 +25,12 @@ __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
   return (uint16_t)(b >> 16);
 }
 
+// floor(x / d) for the multiplier m and shift l of a divisor d (FastDiv in
+// the host interface).
+__device__ __forceinline__ uint32_t fdiv(uint32_t x, uint32_t m, uint32_t l) {
+  return (uint32_t)(((uint64_t)__umulhi(m, x) + x) >> l);
+}
+
 template <typename Tc, typename Ts>
 struct Cvt;
 template <>

@@ -418,7 +418,6 @@ void build_lift(const ttc_tt* x, const ttc_tt* y, BlockKind kind, int k, const v
     c.r1 = r1;
     c.d0 = d0;
     c.d1 = d1;
-    c.line_begin = lines;
     c.src = src;
     c.dst = out_cores[nc];
     lines += d0 * n;

@@ -89,14 +89,36 @@ enum LiftOp {
   LIFT_ABSORB_M = 5,     // dst (ka, n, r1 * Q): sum_b T[(a, g), (b, d)] G[b, i, s]
   LIFT_DELTA_SPLIT = 6   // dst (r0 * Q, n, kd): G[y, i, g] if d == d', src r1 = kg
 };
+// Unsigned division by a run-time invariant d with one multiply-high
+// (Granlund and Montgomery, "Division by invariant integers using
+// multiplication", 1994, sec. 4): with l = ceil(log2 d) and
+// m = floor(2^32 (2^l - d) / d) + 1, floor(x / d) = (mulhi(m, x) + x) >> l
+// for every 32-bit x.
+struct FastDiv {
+  uint32_t m, l;
+};
+inline FastDiv make_fastdiv(uint32_t d) {
+  FastDiv f;
+  uint32_t l = 0;
+  while (l < 32 && ((uint64_t)1 << l) < d) ++l;
+  f.l = l;
+  f.m = (uint32_t)((((uint64_t)1 << 32) * (((uint64_t)1 << l) - d)) / d + 1);
+  return f;
+}
+
 struct LiftCore {
   int op;
   int r0, n, r1;     // source core shape
   int d0, d1;        // destination bond sizes (n is shared)
   int kg, kd;        // LIFT_ABSORB_M / LIFT_DELTA_SPLIT: the carried bond's two factors
-  int line_begin;    // first line (d0 x n lines of d1 elements) of this core
   const void* src;
   void* dst;
+  // filled by launch_lift: the core's items (runs of `vec` consecutive
+  // outputs of one line, w per line), numbered from item_begin (a multiple
+  // of 64, so a wave's items lie in one core)
+  long item_begin, items;
+  int vec, w;
+  FastDiv fw, fn;
 };
 #define TTC_MAX_LIFT (2 * TTC_MAX_ORDER)
 struct LiftArgs {
@@ -104,6 +126,7 @@ struct LiftArgs {
   int Q;             // columns of K
   int kr;            // rows of K
   const void* K;     // compute type
+  FastDiv fq;        // filled by launch_lift
   LiftCore c[TTC_MAX_LIFT];
 };
 

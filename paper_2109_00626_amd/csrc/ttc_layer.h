@@ -15,6 +15,9 @@ struct IdxMap {
   long ms0, ms1, ms2, ns0, ns1;
 };
 
+// Output tile of the GEMM kernel (workgroup tile M x N).
+enum GemmTile { GEMM_TILE_128x128 = 0, GEMM_TILE_32x128 = 1, GEMM_TILE_128x32 = 2, GEMM_TILE_128x64 = 3 };
+
 // C (M x N, row-major, ldc) = alpha * A . B with
 //   A(m, k) = a_kc ? A[m * lda + k] : A[k * lda + m]
 //   B(k, n) = b_kc ? B[n * ldb + k] : B[k * ldb + n]
@@ -32,6 +35,7 @@ struct GemmArgs {
   bool vec_a, vec_b;  // 16-byte vector loads allowed
   bool mapped;        // C element (m, n) goes to C[map(m, n)] (splits == 1)
   IdxMap map;
+  GemmTile tile;
 };
 
 // dst[m * N + n] = src[map(m, n)] (the inverse of a mapped GEMM store).
@@ -72,6 +76,9 @@ struct TilePermArgs {
   long tiles;
   const float* src;
   float* dst;
+  uint16_t* dst16;                // dir 0: BF16 destination instead of dst
+  bool vec;                       // Bp, Bm multiples of 4: 16-byte global accesses
+  FastDiv fgp, fgm, fjl;          // division by Bp / v, Bm / v and Jl (v = 4 if vec)
 };
 
 hipError_t launch_gemm(bool a_kc, bool b_kc, bool bf16, const GemmArgs& g, hipStream_t s);
@@ -103,6 +110,10 @@ hipError_t launch_cvt16_both(const float* src, uint16_t* dst, uint16_t* dst_t, l
 constexpr int kTilePermElems = 8192;
 hipError_t launch_tile_permute(const TilePermArgs& p, hipStream_t s);
 int gemm_bk(bool bf16);
+// The tile for an M x N product (thin tiles for a side of at most 32 or 64)
+// and its dimensions.
+GemmTile gemm_tile(int M, int N);
+void gemm_tile_dims(GemmTile t, int* tm, int* tn);
 hipError_t launch_permute(const PermArgs& p, hipStream_t s);
 hipError_t launch_gather(const GatherArgs& a, hipStream_t s);
 // Core (R, I, J, R1) <-> its (J R) x (I R1) matrix Wp[(j, r), (i, r1)];

@@ -91,6 +91,7 @@ int main() {
   expect("mpo query", ttm_apply_query(&w, &v.d, out_ranks, &elems), TTC_OK);
   expect("dense query", ttm_apply_dense_query(&w, 37, TTC_PREC_AUTO, TTC_SCHED_CORES, 1, &ws), TTC_OK);
   expect("dense query dense", ttm_apply_dense_query(&w, 37, TTC_PREC_BF16, TTC_SCHED_DENSE, 1, &ws), TTC_OK);
+  expect("dense query saved", ttm_apply_dense_query(&w, 37, TTC_PREC_AUTO, TTC_SCHED_CORES_SAVED, 0, &ws), TTC_OK);
   expect("mse query", ttc_mse_loss_query(1001, &ws), TTC_OK);
   for (int c = 0; c <= 4; ++c) expect("grad query", tt_contract_inner_bwd_query(&x.d, &y.d, c, &ws), TTC_OK);
   // TT-SVD and rounding queries

@@ -188,9 +188,11 @@ def test_grad_query(lib, abi):
 
 
 def test_layer_schedule_queries(lib, abi):
-    """Both layer schedules are accepted; AUTO takes the one with fewer FLOPs
+    """Every layer schedule is accepted; AUTO takes the one with fewer FLOPs
     (the dense one for the 4096 x 4096 order-4 layer); the core-by-core
-    backward keeps its three 8192 * 512 * 256 intermediates."""
+    backward keeps its three 8192 * 512 * 256 intermediates and two gradient
+    buffers; the saving schedule's forward asks for the backward's
+    workspace; an unknown schedule is refused."""
     s = C.layer4_shape()
     rows = (c_int32 * 4)(*s.modes)
     cols = (c_int32 * 4)(*s.cols)
@@ -198,7 +200,7 @@ def test_layer_schedule_queries(lib, abi):
     cores = (c_void_p * 4)(*[FAKE] * 4)
     m = abi.TTM(4, rows, cols, rk, 1, cores)
     ws = {}
-    for name in ("auto", "dense", "cores"):
+    for name in ("auto", "dense", "cores", "cores_saved"):
         for bwd in (0, 1):
             b = c_size_t(0)
             assert lib.ttm_apply_dense_query(byref(m), 8192, abi.PREC["f32"], abi.SCHED[name], bwd, byref(b)) == 0
@@ -207,6 +209,10 @@ def test_layer_schedule_queries(lib, abi):
     inter = 8192 * 512 * 8 * 32 * 4   # bytes of one intermediate
     assert ws["cores", 1] >= 3 * inter + 2 * inter
     assert 2 * inter <= ws["cores", 0] < 3 * inter
+    assert ws["cores_saved", 0] == ws["cores_saved", 1] == ws["cores", 1]
+    b = c_size_t(0)
+    assert status_name(abi, lib.ttm_apply_dense_query(byref(m), 8192, abi.PREC["f32"], 4, 0, byref(b))) == \
+        "TTC_ERR_UNSUPPORTED"
 
 
 def test_svd_query_caps_and_errors(lib, abi):

@@ -20,7 +20,17 @@ def _upload(a):
     return torch.from_numpy(np.ascontiguousarray(a)).to(torch.float32).cuda()
 
 
-@pytest.mark.parametrize("sched", ["dense", "cores"])
+def _ws(ttc, wg, batch, prec, sched):
+    """The workspace kept from the forward to the backward for the schedule
+    that saves its intermediates (None for the others: the call allocates)."""
+    if sched != "cores_saved":
+        return None
+    import torch
+    need = ttc.ttm_apply_dense_query(wg, batch, prec, sched, backward=True)
+    return torch.empty(need, dtype=torch.uint8, device="cuda")
+
+
+@pytest.mark.parametrize("sched", ["dense", "cores", "cores_saved"])
 @pytest.mark.parametrize("prec", ["f32", "bf16"])
 def test_layer_fd_instance(ttc, prec, sched):
     """Order 3, I = J = 4, ranks (1,4,4,1), batch 8: forward, loss and every
@@ -35,17 +45,19 @@ def test_layer_fd_instance(ttc, prec, sched):
     Xs, Ts = to_np(Xg), to_np(Tg)
     ref = O.layer_forward_backward(ws, Xs, Ts) if prec == "f32" else O.layer_forward_backward(w, X, T)
     tol = TOL[prec]
-    Y = ttc.ttm_apply_dense(wg, Xg, prec=prec, sched=sched)
+    wsp = _ws(ttc, wg, 8, prec, sched)
+    Y = ttc.ttm_apply_dense(wg, Xg, prec=prec, sched=sched, ws=wsp)
     assert rel_err(to_np(Y), ref["Y"]) <= tol
     L, dY = ttc.ttc_mse_loss(Y, Tg)
     assert abs(L.item() - ref["L"]) <= tol * ref["L"]
     assert rel_err(to_np(dY), ref["dY"]) <= tol
-    dX, dG = ttc.ttm_apply_dense_bwd(wg, Xg, dY, prec=prec, sched=sched)
+    dX, dG = ttc.ttm_apply_dense_bwd(wg, Xg, dY, prec=prec, sched=sched, ws=wsp)
     assert rel_err(to_np(dX), ref["dX"]) <= tol
     assert max_core_rel([to_np(g) for g in dG], ref["dG"]) <= tol
 
 
-def test_layer_autograd_matches_oracle(ttc):
+@pytest.mark.parametrize("sched", ["auto", "cores_saved"])
+def test_layer_autograd_matches_oracle(ttc, sched):
     import torch
     s = C.TTShape([4, 2, 3], [1, 3, 5, 1], [3, 4, 2])   # rectangular: 24 x 24
     w = C.gen_tt_np(C.SEED_LAYER, 21, s)
@@ -56,7 +68,7 @@ def test_layer_autograd_matches_oracle(ttc):
     ref = O.layer_forward_backward(ws, to_np(Xg), to_np(Tg))
     cores = [c.clone().requires_grad_(True) for c in wg]
     xv = Xg.clone().requires_grad_(True)
-    Y = ttc.tt_linear(xv, cores)
+    Y = ttc.tt_linear(xv, cores, sched=sched)
     L, dY = ttc.ttc_mse_loss(Y.detach(), Tg)
     Y.backward(dY)
     assert rel_err(to_np(xv.grad), ref["dX"]) <= TOL["f32"]
@@ -87,7 +99,7 @@ def _layer4(ttc):
 
 
 @pytest.mark.parametrize("prec", ["f32", "bf16"])
-@pytest.mark.parametrize("sched", ["dense", "cores"])
+@pytest.mark.parametrize("sched", ["dense", "cores", "cores_saved"])
 def test_layer4_full_size(ttc, sched, prec):
     """The full 8192 x 4096 batch through both schedules, FP32 and the BF16
     MFMA option: Y, the loss, dY, dX and every core gradient against the
@@ -96,14 +108,16 @@ def test_layer4_full_size(ttc, sched, prec):
     (Y is linear in each core)."""
     d = _layer4(ttc)
     ref, tol = d[prec], TOL[prec]
-    Y = ttc.ttm_apply_dense(d["wg"], d["Xg"], prec=prec, sched=sched)
+    wsp = _ws(ttc, d["wg"], 8192, prec, sched)
+    Y = ttc.ttm_apply_dense(d["wg"], d["Xg"], prec=prec, sched=sched, ws=wsp)
     Yn = to_np(Y)
     assert rel_err(Yn, ref["Y"]) <= tol
     L, dY = ttc.ttc_mse_loss(Y, d["Tg"])
     assert abs(L.item() - ref["L"]) <= tol * ref["L"]
     dYn = to_np(dY)
     assert rel_err(dYn, ref["dY"]) <= tol
-    dX, dG = ttc.ttm_apply_dense_bwd(d["wg"], d["Xg"], dY, prec=prec, sched=sched)
+    dX, dG = ttc.ttm_apply_dense_bwd(d["wg"], d["Xg"], dY, prec=prec, sched=sched, ws=wsp)
+    del wsp
     assert rel_err(to_np(dX), ref["dX"]) <= tol
     dGn = [to_np(g) for g in dG]
     errs = [rel_err(g, r) for g, r in zip(dGn, ref["dG"])]
@@ -115,7 +129,7 @@ def test_layer4_full_size(ttc, sched, prec):
         assert abs(got - euler) <= (1e-4 if prec == "f32" else 2e-2) * abs(euler)
 
 
-@pytest.mark.parametrize("sched", ["cores", "dense"])
+@pytest.mark.parametrize("sched", ["cores", "dense", "cores_saved"])
 @pytest.mark.parametrize("dims", [
     ([4, 2, 3], [1, 3, 5, 1], [3, 4, 2], 37),       # rectangular, ragged batch
     ([5], [1, 1], [7], 3),                          # order 1
@@ -134,10 +148,11 @@ def test_layer_cores_schedule(ttc, dims, sched):
     wg, ws = to_gpu(w, "f32")
     Xg, Tg = _upload(X), _upload(T)
     ref = O.layer_forward_backward(ws, to_np(Xg), to_np(Tg))
-    Y = ttc.ttm_apply_dense(wg, Xg, sched=sched)
+    wsp = _ws(ttc, wg, B, "auto", sched)
+    Y = ttc.ttm_apply_dense(wg, Xg, sched=sched, ws=wsp)
     assert rel_err(to_np(Y), ref["Y"]) <= TOL["f32"]
     _, dY = ttc.ttc_mse_loss(Y, Tg)
-    dX, dG = ttc.ttm_apply_dense_bwd(wg, Xg, dY, sched=sched)
+    dX, dG = ttc.ttm_apply_dense_bwd(wg, Xg, dY, sched=sched, ws=wsp)
     assert rel_err(to_np(dX), ref["dX"]) <= TOL["f32"]
     assert max_core_rel([to_np(g) for g in dG], ref["dG"]) <= TOL["f32"]
 
