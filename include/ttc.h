@@ -137,7 +137,10 @@ typedef struct {
  * way z = sum W_c .* V_c, accumulated in FP64.  X and Y need equal order and
  * mode sizes; their ranks may differ.
  * x, y:   descriptors, same dtype.
- * prec:   AUTO, or the precision AUTO would pick.
+ * prec:   AUTO, or the precision AUTO would pick, or BF16 for BF16 cores
+ *         with every rank <= 128 (else TTC_ERR_UNSUPPORTED): the steps on
+ *         BF16 MFMA, the interface carried as a BF16 hi / lo pair (about 16
+ *         significant bits) with FP32 sums.
  * d_out:  device pointer to one double (written).
  * d_ws:   device scratch of at least the size tt_contract_inner_query
  *         returns (may be NULL when that size is 0).
@@ -367,7 +370,10 @@ ttc_status tt_round(const ttc_tt* x, double eps, int32_t max_rank, int32_t* rank
  *                   junction_offset[p] elements (offsets from
  *                   tt_batch_plan_info).
  * Pairs need order >= 2 (SUFFIX2: >= 3) and order <= 32; X and Y of a pair
- * share dtype (FP32 or BF16) and mode sizes.  The plan copies every
+ * share dtype (FP32 or BF16) and mode sizes.  prec: AUTO lets the tuner pick
+ * among every schedule; F32 keeps the steps on FP32 MFMA (BF16 cores are
+ * widened); BF16 (BF16 cores only, else TTC_ERR_UNSUPPORTED) runs every step
+ * on BF16 MFMA with FP32 sums (mode 4 below).  The plan copies every
  * descriptor (shapes and core pointers) when it is created; the core buffers
  * must stay alive and unchanged in place until the plan is destroyed.
  * tt_batch_plan_create synchronises the device once (descriptor upload and

@@ -53,6 +53,7 @@ struct ttc_plan {
   int n = 0;
   uint32_t ops = 0;
   ttc_dtype dt = TTC_F32;
+  ttc_prec prec = TTC_PREC_AUTO;  // BF16: BF16-MFMA steps only; F32: FP32-MFMA steps only
   int device = 0;
   int cus = 256;
   std::vector<PairHost> pairs;
@@ -386,6 +387,7 @@ std::string cache_key(const ttc_plan* P) {
   }
   mix(P->ops);
   mix(P->dt);
+  mix(P->prec);
   std::ostringstream os;
   os << "gfx950|abi" << TTC_ABI_VERSION << "|s5|" << std::hex << h;
   return os.str();
@@ -430,14 +432,19 @@ ttc_status autotune(ttc_plan* P) {
     // the BF16-MFMA variant takes BF16 cores only; FP32 plans keep the tuner's choice
     if (want == 4 && P->dt != TTC_BF16) want = -1;
   }
+  // the plan's precision: BF16 keeps only the BF16-MFMA schedule, F32 every
+  // schedule but that one
+  if (P->prec == TTC_PREC_BF16) want = 4;
+  if (P->prec == TTC_PREC_F32 && want == 4) want = -1;
+  const bool no16 = P->prec == TTC_PREC_F32;
   LaunchCfg best;
-  if (cache_lookup(key, &best) && (want < 0 || want == best.mode)) {
+  if (cache_lookup(key, &best) && (want < 0 || want == best.mode) && !(no16 && best.mode == 4)) {
     P->mode = best.mode;
     P->cfg = best;
     return upload_assignment(P, best, &P->grid, &P->lds_elems);
   }
   std::vector<LaunchCfg> cands;
-  if (P->dt == TTC_BF16 && (want < 0 || want == 4))
+  if (P->dt == TTC_BF16 && !no16 && (want < 0 || want == 4))
     for (int pc = 1; pc <= lds16_kernel_per_cu(P); ++pc) cands.push_back({4, 256, pc});
   if (want < 0 || want == 3)
     for (int pc = 1; pc <= lds_kernel_per_cu(P, 1); ++pc) cands.push_back({3, 256, pc});
@@ -454,6 +461,7 @@ ttc_status autotune(ttc_plan* P) {
     cands.push_back({0, 256, 2});
   }
   if (want < 0 || want == 1) cands.push_back({1, 256, 1});
+  if (cands.empty()) return fail(TTC_ERR_UNSUPPORTED, "no schedule of the plan's precision fits these pairs");
   double* d_inner = nullptr;
   float* d_junc = nullptr;
   TTC_HIP(hipMalloc(&d_inner, sizeof(double) * std::max(P->n, 1)));
@@ -559,13 +567,17 @@ ttc_status tt_batch_plan_create(const ttc_pair* pairs, int32_t n, uint32_t ops, 
   *plan = nullptr;
   if (!pairs || n < 1) return fail(TTC_ERR_NULL, "no pairs");
   if (ops == 0 || (ops & ~(TTC_OP_INNER | TTC_OP_SUFFIX2))) return fail(TTC_ERR_UNSUPPORTED, "bad ops mask");
-  if (prec != TTC_PREC_AUTO && prec != TTC_PREC_F32) return fail(TTC_ERR_UNSUPPORTED, "batched precision is FP32");
+  if (prec != TTC_PREC_AUTO && prec != TTC_PREC_F32 && prec != TTC_PREC_BF16)
+    return fail(TTC_ERR_UNSUPPORTED, "batched precision is AUTO, F32 or BF16");
   ttc_dtype dt = TTC_F32;
   for (int i = 0; i < n; ++i) TTC_TRY(check_pair_desc(pairs[i], i, ops, &dt));
+  if (prec == TTC_PREC_BF16 && dt != TTC_BF16)
+    return fail(TTC_ERR_UNSUPPORTED, "BF16 precision needs BF16 cores (the BF16-MFMA steps)");
   ttc_plan* P = new ttc_plan();
   P->n = n;
   P->ops = ops;
   P->dt = dt;
+  P->prec = prec;
   P->buf_elems = 16 * (16 + 4);  // V_N = [1] padded
   const size_t esz = dt == TTC_BF16 ? 2 : 4;
   P->pairs.resize(n);

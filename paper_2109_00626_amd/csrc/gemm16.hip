@@ -37,20 +37,6 @@ size_t gemm16_lds_bytes() { return (size_t)2 * 2 * G16_BM * G16_P * sizeof(uint1
 
 namespace {
 
-// Tile of the output handled by workgroup b: XCD-contiguous ranges, eight
-// tile rows per group inside a range.
-__device__ __forceinline__ void g16_tile(int b, int tiles_m, int tiles_n, int per_xcd, int* tm, int* tn) {
-  int t = b;
-  if (per_xcd) t = (b & 7) * per_xcd + (b >> 3);
-  const int GM = 8;
-  const int span = GM * tiles_n;
-  const int first = (t / span) * GM;
-  const int gsz = min(tiles_m - first, GM);
-  const int l = t - (t / span) * span;
-  *tm = first + l % gsz;
-  *tn = l / gsz;
-}
-
 __device__ __forceinline__ void g16_load(const uint16_t* P, long ld, int row0, int nrows, int k0, int kend,
                                          u32x4* r) {
 #pragma unroll
@@ -81,7 +67,7 @@ __global__ __launch_bounds__(G16_THREADS) void gemm16_kernel(Gemm16Args g) {
   uint16_t* Bs = As + 2 * G16_BM * G16_P;             // [2][256][72]
   const int tiles_m = (g.M + G16_BM - 1) / G16_BM, tiles_n = (g.N + G16_BN - 1) / G16_BN;
   int tm, tn;
-  g16_tile(blockIdx.x, tiles_m, tiles_n, g.per_xcd, &tm, &tn);
+  xcd_tile(blockIdx.x, tiles_m, tiles_n, g.per_xcd, &tm, &tn);
   const int m0 = tm * G16_BM, n0 = tn * G16_BN;
   const int kper = ((g.K + g.splits - 1) / g.splits + G16_BK - 1) / G16_BK * G16_BK;
   const int kbeg = blockIdx.y * kper;

@@ -3,12 +3,13 @@
 // step in its cheaper contraction order, cores streamed from HBM.  Used for
 // the inner product, the junction of a prefix or suffix contraction and the
 // interfaces of the inner-product gradient when the pair qualifies (FP32 or
-// BF16 cores, ranks <= 128).  Left-to-right sweeps run as right-to-left
+// BF16 cores, ranks <= 128).  M16 (BF16 cores, precision BF16): the steps of
+// sweep_lds16.hpp on BF16 MFMA, the interface held as BF16 hi / lo planes.  Left-to-right sweeps run as right-to-left
 // sweeps of the reversed pair with rank-transposed cores: the step
 //   sum_i G_x[:, i, :]^T W G_y[:, i, :]
 // of a left-to-right sweep is the right-to-left step on cores G'[a, i, b] =
 // G[b, i, a].
-#include "sweep_lds.hpp"
+#include "sweep_lds16.hpp"
 #include "ttc_device.hpp"
 #include "ttc_internal.h"
 
@@ -27,9 +28,20 @@ __device__ __forceinline__ void store_iface(float* dst, const TTC_LDS float* buf
   }
 }
 
-template <typename Tin>
+// The same from BF16 planes (hi at V, lo at V + lo).
+__device__ __forceinline__ void store_iface16(float* dst, const TTC_LDS uint16_t* V, int lo, int R, int P,
+                                              bool plain) {
+  const int tp = lds16_pitch(R), np = lds16_pitch(P);
+  for (int e = threadIdx.x; e < R * P; e += blockDim.x) {
+    const int r = e / P, c = e - r * P;
+    dst[e] = lds16_get(V, lo, plain ? r * np + c : c * tp + r);
+  }
+}
+
+template <typename Tin, bool M16>
 __global__ __launch_bounds__(256, 2) void pair_lds_kernel(PairLdsArgs args) {
   constexpr int NW = 4;
+  static_assert(!M16 || sizeof(Tin) == 2, "BF16 MFMA steps: BF16 cores");
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double red[16];
   __shared__ TTDev sx, sy;
@@ -48,7 +60,16 @@ __global__ __launch_bounds__(256, 2) void pair_lds_kernel(PairLdsArgs args) {
     }
   }
   TTC_LDS float* const buf = (TTC_LDS float*)smem;
-  for (int e = threadIdx.x; e < 16 * lds_pitch(1); e += blockDim.x) buf[e] = (e == 0) ? 1.f : 0.f;
+  TTC_LDS uint16_t* const pl = (TTC_LDS uint16_t*)smem;  // M16: hi plane; lo plane at pl + lo
+  const int lo = args.lo;
+  if constexpr (M16) {
+    for (int e = threadIdx.x; e < 16 * lds16_pitch(1); e += blockDim.x) {
+      pl[e] = (e == 0) ? (uint16_t)0x3F80u : (uint16_t)0;
+      pl[lo + e] = 0;
+    }
+  } else {
+    for (int e = threadIdx.x; e < 16 * lds_pitch(1); e += blockDim.x) buf[e] = (e == 0) ? 1.f : 0.f;
+  }
   __syncthreads();
   const int N = sx.order, stop = a.stop;
   if (a.all && threadIdx.x == 0) a.all[(long)(a.slot_a * N + a.slot_b) * a.all_stride] = 1.f;
@@ -73,16 +94,23 @@ __global__ __launch_bounds__(256, 2) void pair_lds_kernel(PairLdsArgs args) {
       op.Nb = sy.ranks[k];
       op.Kb = sy.ranks[k + 1];
     }
-    lds_step_inplace<Tin, NW>(op, buf, yf == yf_next);
+    if constexpr (M16) lds16_step_inplace<NW>(op, pl, lo, yf == yf_next, nullptr);
+    else lds_step_inplace<Tin, NW>(op, buf, yf == yf_next);
     // (the step ends with a barrier; the next step overwrites buf only after
     // its own barrier, which every thread reaches after these stores)
-    if (a.all && k >= 1)
-      store_iface(a.all + (long)(a.slot_a * k + a.slot_b) * a.all_stride, buf, sx.ranks[k], sy.ranks[k], yf_next);
-    if (k == stop && a.out) store_iface(a.out, buf, sx.ranks[k], sy.ranks[k], yf_next);
+    if constexpr (M16) {
+      if (k == stop && a.out) store_iface16(a.out, pl, lo, sx.ranks[k], sy.ranks[k], yf_next);
+    } else {
+      if (a.all && k >= 1)
+        store_iface(a.all + (long)(a.slot_a * k + a.slot_b) * a.all_stride, buf, sx.ranks[k], sy.ranks[k], yf_next);
+      if (k == stop && a.out) store_iface(a.out, buf, sx.ranks[k], sy.ranks[k], yf_next);
+    }
     yf = yf_next;
   }
   if (a.inner) {
-    double s = lds_final<Tin, NW>(sx.cores[0], sy.cores[0], sx.modes[0], sx.ranks[1], sy.ranks[1], buf);
+    double s;
+    if constexpr (M16) s = lds16_final<NW>(sx.cores[0], sy.cores[0], sx.modes[0], sx.ranks[1], sy.ranks[1], pl, lo);
+    else s = lds_final<Tin, NW>(sx.cores[0], sy.cores[0], sx.modes[0], sx.ranks[1], sy.ranks[1], buf);
     s = wg_sum_f64(s, red);
     if (threadIdx.x == 0) *a.inner = s;
   }
@@ -104,11 +132,14 @@ __global__ __launch_bounds__(256) void core_reverse_kernel(CoreRevArgs a) {
   }
 }
 
-// Floats of the one in-place interface buffer for a side.
-int side_lds_floats(const PairLdsSide& s) {
-  int m = 16 * lds_pitch(1);
-  for (int b = s.stop; b <= s.x.order; ++b) m = std::max(m, lds_iface_elems(s.x.ranks[b], s.y.ranks[b]));
-  return m;
+// Floats of the one in-place interface buffer for a side; m16: elements of
+// each BF16 plane (a multiple of 8, so the lo plane starts 16-byte aligned;
+// two planes take as many bytes as that many floats).
+int side_lds_floats(const PairLdsSide& s, bool m16) {
+  int m = m16 ? 16 * lds16_pitch(1) : 16 * lds_pitch(1);
+  for (int b = s.stop; b <= s.x.order; ++b)
+    m = std::max(m, m16 ? lds16_iface_elems(s.x.ranks[b], s.y.ranks[b]) : lds_iface_elems(s.x.ranks[b], s.y.ranks[b]));
+  return (m + 7) & ~7;
 }
 
 }  // namespace
@@ -121,24 +152,31 @@ bool pair_lds_ok(const TTDev& x, const TTDev& y) {
   return true;
 }
 
-hipError_t launch_pair_lds(ttc_dtype dt, const PairLdsArgs& a, int nsides, hipStream_t s) {
+hipError_t launch_pair_lds(ttc_dtype dt, const PairLdsArgs& in, int nsides, hipStream_t s) {
+  PairLdsArgs a = in;
+  const bool m16 = a.m16 && dt == TTC_BF16;
   int floats = 0;
-  for (int q = 0; q < nsides; ++q) floats = std::max(floats, side_lds_floats(a.side[q]));
+  for (int q = 0; q < nsides; ++q) floats = std::max(floats, side_lds_floats(a.side[q], m16));
+  a.lo = floats;
   const int bytes = floats * (int)sizeof(float);
   static std::atomic<bool> done[kMaxDevices];
   const hipError_t e = once_per_device(done, [] {
     // the largest buffer any qualifying pair needs (ranks 128)
-    const int most = lds_iface_elems(128, 128) * (int)sizeof(float);
-    hipError_t r = hipFuncSetAttribute(reinterpret_cast<const void*>(&pair_lds_kernel<float>),
+    const int most = std::max(lds_iface_elems(128, 128), (lds16_iface_elems(128, 128) + 7) & ~7) * (int)sizeof(float);
+    hipError_t r = hipFuncSetAttribute(reinterpret_cast<const void*>(&pair_lds_kernel<float, false>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, most);
     if (r == hipSuccess)
-      r = hipFuncSetAttribute(reinterpret_cast<const void*>(&pair_lds_kernel<bf16_t>),
+      r = hipFuncSetAttribute(reinterpret_cast<const void*>(&pair_lds_kernel<bf16_t, false>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, most);
+    if (r == hipSuccess)
+      r = hipFuncSetAttribute(reinterpret_cast<const void*>(&pair_lds_kernel<bf16_t, true>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, most);
     return r;
   });
   if (e != hipSuccess) return e;
-  if (dt == TTC_BF16) hipLaunchKernelGGL((pair_lds_kernel<bf16_t>), dim3(nsides), dim3(256), bytes, s, a);
-  else hipLaunchKernelGGL((pair_lds_kernel<float>), dim3(nsides), dim3(256), bytes, s, a);
+  if (m16) hipLaunchKernelGGL((pair_lds_kernel<bf16_t, true>), dim3(nsides), dim3(256), bytes, s, a);
+  else if (dt == TTC_BF16) hipLaunchKernelGGL((pair_lds_kernel<bf16_t, false>), dim3(nsides), dim3(256), bytes, s, a);
+  else hipLaunchKernelGGL((pair_lds_kernel<float, false>), dim3(nsides), dim3(256), bytes, s, a);
   return hipGetLastError();
 }
 

@@ -31,6 +31,23 @@ __device__ __forceinline__ uint32_t fdiv(uint32_t x, uint32_t m, uint32_t l) {
   return (uint32_t)(((uint64_t)__umulhi(m, x) + x) >> l);
 }
 
+// Output tile (tm, tn) of workgroup b in a grid of tiles_m x tiles_n tiles.
+// Workgroups are dealt to the eight XCDs round-robin; with per_xcd (the
+// tiles per XCD, tiles a multiple of 8) the index is remapped so that each
+// XCD walks a contiguous range of tiles, in groups of eight tile rows, which
+// keeps the operand panels one XCD touches in its own L2.
+__device__ __forceinline__ void xcd_tile(int b, int tiles_m, int tiles_n, int per_xcd, int* tm, int* tn) {
+  int t = b;
+  if (per_xcd) t = (b & 7) * per_xcd + (b >> 3);
+  const int GM = 8;
+  const int span = GM * tiles_n;
+  const int first = (t / span) * GM;
+  const int gsz = min(tiles_m - first, GM);
+  const int l = t - (t / span) * span;
+  *tm = first + l % gsz;
+  *tn = l / gsz;
+}
+
 template <typename Tc, typename Ts>
 struct Cvt;
 template <>

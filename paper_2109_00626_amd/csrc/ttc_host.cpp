@@ -313,8 +313,9 @@ ttc_status run_junction(const ttc_tt* x, const ttc_tt* y, BlockKind kind, int k,
 }
 
 // Bidirectional inner product meeting at bond N/2.
+// m16: BF16 cores on the BF16-MFMA steps (LDS path only).
 ttc_status run_inner(const ttc_tt* x, const ttc_tt* y, double* d_out, Arena& ws, size_t ws_bytes, bool sizing,
-                     hipStream_t s) {
+                     hipStream_t s, bool m16 = false) {
   if (lds_path(x, y) && x->order >= 4) {
     // two half sweeps at once, one workgroup each, meeting at bond c: V_c right
     // to left over cores c..N-1, W_c as the right-to-left sweep of the
@@ -335,6 +336,7 @@ ttc_status run_inner(const ttc_tt* x, const ttc_tt* y, double* d_out, Arena& ws,
     if (ws.off > ws_bytes) return fail(TTC_ERR_WORKSPACE, "workspace too small");
     pa.side[0].out = reinterpret_cast<float*>(V);
     pa.side[1].out = reinterpret_cast<float*>(W);
+    pa.m16 = m16;
     TTC_HIP(launch_core_reverse(ra, s));
     TTC_HIP(launch_pair_lds(x->dtype, pa, 2, s));
     TTC_HIP(launch_meet(x->dtype, W, V, (int)rp, d_out, s));
@@ -349,6 +351,7 @@ ttc_status run_inner(const ttc_tt* x, const ttc_tt* y, double* d_out, Arena& ws,
     pa.side[0].y = to_dev(y);
     pa.side[0].stop = 1;
     pa.side[0].inner = d_out;
+    pa.m16 = m16;
     TTC_HIP(launch_pair_lds(x->dtype, pa, 1, s));
     return TTC_OK;
   }
@@ -382,6 +385,15 @@ ttc_status run_inner(const ttc_tt* x, const ttc_tt* y, double* d_out, Arena& ws,
   a.chain = sz.chain;
   TTC_HIP(launch_sweep(x->dtype, a, 2, sz.lds, s));
   TTC_HIP(launch_meet(x->dtype, W, V, (int)rp, d_out, s));
+  return TTC_OK;
+}
+
+// Precision of an inner product: AUTO, the precision AUTO picks, or BF16
+// for BF16 cores on the LDS path (every rank <= 128): the BF16-MFMA steps.
+ttc_status check_inner_prec(const ttc_tt* x, const ttc_tt* y, ttc_prec prec) {
+  if (prec != TTC_PREC_BF16) return check_prec(prec, x->dtype);
+  if (x->dtype != TTC_BF16) return fail(TTC_ERR_UNSUPPORTED, "BF16 precision needs BF16 cores");
+  if (!lds_path(x, y)) return fail(TTC_ERR_UNSUPPORTED, "BF16 MFMA steps need every rank <= 128");
   return TTC_OK;
 }
 
@@ -467,7 +479,7 @@ int32_t ttc_abi_version(void) { return TTC_ABI_VERSION; }
 
 ttc_status tt_contract_inner_query(const ttc_tt* x, const ttc_tt* y, ttc_prec prec, size_t* ws_bytes) {
   TTC_TRY(check_pair(x, y));
-  TTC_TRY(check_prec(prec, x->dtype));
+  TTC_TRY(check_inner_prec(x, y, prec));
   if (!ws_bytes) return fail(TTC_ERR_NULL, "ws_bytes is NULL");
   Arena a(nullptr);
   TTC_TRY(run_inner(x, y, nullptr, a, 0, true, 0));
@@ -478,7 +490,7 @@ ttc_status tt_contract_inner_query(const ttc_tt* x, const ttc_tt* y, ttc_prec pr
 ttc_status tt_contract_inner(const ttc_tt* x, const ttc_tt* y, ttc_prec prec, double* d_out, void* d_ws,
                              size_t ws_bytes, void* stream) {
   TTC_TRY(check_pair(x, y));
-  TTC_TRY(check_prec(prec, x->dtype));
+  TTC_TRY(check_inner_prec(x, y, prec));
   if (!d_out) return fail(TTC_ERR_NULL, "d_out is NULL");
   size_t need = 0;
   TTC_TRY(tt_contract_inner_query(x, y, prec, &need));
@@ -486,7 +498,7 @@ ttc_status tt_contract_inner(const ttc_tt* x, const ttc_tt* y, ttc_prec prec, do
   if (need && !d_ws) return fail(TTC_ERR_NULL, "d_ws is NULL");
   TTC_TRY(ensure_init());
   Arena a(d_ws);
-  return run_inner(x, y, d_out, a, ws_bytes, false, (hipStream_t)stream);
+  return run_inner(x, y, d_out, a, ws_bytes, false, (hipStream_t)stream, prec == TTC_PREC_BF16);
 }
 
 ttc_status tt_contract_modes_query(const ttc_tt* x, const ttc_tt* y, const int32_t* modes, int32_t n_modes,

@@ -187,6 +187,8 @@ struct PairLdsSide {
 };
 struct PairLdsArgs {
   PairLdsSide side[2];
+  bool m16;  // BF16 cores on BF16 MFMA (interface as BF16 hi / lo planes)
+  int lo;    // set by launch_pair_lds: elements of one plane (m16)
 };
 // True when the LDS-resident sweep handles the pair (FP32/BF16, ranks <= 128).
 bool pair_lds_ok(const TTDev& x, const TTDev& y);

@@ -93,6 +93,13 @@ def test_inner_validation(lib, abi):
     assert status_name(abi, lib.tt_contract_inner_query(byref(x.s), byref(d64.s), 0, byref(need))) == "TTC_ERR_DTYPE"
     assert status_name(abi, lib.tt_contract_inner_query(None, byref(y.s), 0, byref(need))) == "TTC_ERR_NULL"
     assert status_name(abi, lib.tt_contract_inner_query(byref(x.s), byref(y.s), 1, byref(need))) == "TTC_ERR_UNSUPPORTED"
+    # BF16 precision: BF16 cores with every rank <= 128 only
+    assert status_name(abi, lib.tt_contract_inner_query(byref(x.s), byref(y.s), 3, byref(need))) == "TTC_ERR_UNSUPPORTED"
+    xh, yh = Desc(abi, [3, 4], [1, 2, 1], dtype=2), Desc(abi, [3, 4], [1, 5, 1], dtype=2)
+    assert lib.tt_contract_inner_query(byref(xh.s), byref(yh.s), 3, byref(need)) == abi.TTC_OK
+    xhb, yhb = Desc(abi, [3, 4], [1, 200, 1], dtype=2), Desc(abi, [3, 4], [1, 5, 1], dtype=2)
+    assert status_name(abi, lib.tt_contract_inner_query(byref(xhb.s), byref(yhb.s), 3, byref(need))) == \
+        "TTC_ERR_UNSUPPORTED"
     # workspace too small and NULL output: rejected before any launch
     out = c_void_p(FAKE)
     assert status_name(abi, lib.tt_contract_inner(byref(x64.s), byref(y64.s), 0, out, c_void_p(FAKE), 1, None)) == \
@@ -332,3 +339,10 @@ def test_batch_plan_query_errors(lib, abi):
     ex, ey = Desc(abi, [4, 5, 6], [1, 3, 2, 1], 2), Desc(abi, [4, 5, 6], [1, 2, 2, 1], 2)
     arr = (abi.Pair * 2)(abi.Pair(dx.s, dy.s), abi.Pair(ex.s, ey.s))
     assert status_name(abi, lib.tt_batch_plan_query(arr, 2, 3, None, None, None, None, None)) == "TTC_ERR_DTYPE"
+    # plan precision: BF16 needs BF16 cores, FP64 is not a batched precision
+    # (both refused before any device call)
+    arr = (abi.Pair * 1)(abi.Pair(dx.s, dy.s))
+    h = c_void_p(0)
+    assert status_name(abi, lib.tt_batch_plan_create(arr, 1, 3, abi.PREC["bf16"], byref(h))) == "TTC_ERR_UNSUPPORTED"
+    assert status_name(abi, lib.tt_batch_plan_create(arr, 1, 3, abi.PREC["f64"], byref(h))) == "TTC_ERR_UNSUPPORTED"
+    assert not h.value

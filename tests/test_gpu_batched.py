@@ -357,3 +357,38 @@ def test_batch_plans_from_host_threads(ttc, tmp_path, monkeypatch):
         assert cfg == config
         for inner, junc in outs:
             assert np.array_equal(inner, inner0) and np.array_equal(junc, junc0), n
+
+
+@pytest.mark.parametrize("prec", ["bf16", "f32"])
+def test_batch_plan_precision(ttc, prec, monkeypatch):
+    """The plan's precision selects the step arithmetic for BF16 cores: BF16
+    runs the BF16-MFMA schedule, F32 one of the FP32-MFMA schedules, each
+    within its bound against the oracle (total and arithmetic-only); BF16
+    on FP32 cores is refused."""
+    monkeypatch.delenv("TTC_BATCH_MODE", raising=False)
+    monkeypatch.delenv("TTC_AUTOTUNE_CACHE", raising=False)
+    shapes = C.batch_pair_shapes(C.SEED_BATCH + 7, 24)
+    cores64, seen, gpu = [], [], []
+    for p, (sx, sy) in enumerate(shapes):
+        x = C.gen_tt_np(C.SEED_BATCH + 7, 1 + 2 * p, sx)
+        y = C.gen_tt_np(C.SEED_BATCH + 7, 2 + 2 * p, sy)
+        xg, xs = to_gpu(x, "bf16")
+        yg, ys = to_gpu(y, "bf16")
+        cores64.append((x, y))
+        seen.append((xs, ys))
+        gpu.append((xg, yg))
+    plan = ttc.BatchPlan(gpu, prec=prec)
+    if prec == "bf16":
+        assert plan.config["mode"] == "lds1b"
+    else:
+        assert plan.config["mode"] != "lds1b"
+    inner, junc = plan.run()
+    inner = to_np(inner)
+    idx = range(len(shapes))
+    _check_pairs(plan, inner, junc, cores64, idx, TOL["bf16"])
+    _check_pairs(plan, inner, junc, seen, idx, ARITH_BF16["lds1b"] if prec == "bf16" else ARITH_BF16_DEFAULT)
+    xf = [to_gpu(x, "f32")[0] for x, _ in cores64[:2]]
+    yf = [to_gpu(y, "f32")[0] for _, y in cores64[:2]]
+    with pytest.raises(ttc.TTCError) as ei:
+        ttc.BatchPlan(list(zip(xf, yf)), prec="bf16")
+    assert ei.value.name == "TTC_ERR_UNSUPPORTED"

@@ -69,6 +69,47 @@ def test_inner_ragged(ttc, case, dtype):
     assert et <= TOL[dtype]
 
 
+# The BF16-MFMA steps carry the interface and each per-index product as a
+# BF16 hi / lo pair (about 16 significant bits), so each step adds about
+# 2^-17 relative to the arithmetic error; 1e-4 leaves a wide margin for the
+# at most ten steps below.
+ARITH_BF16_MFMA = 1e-4
+
+
+@pytest.mark.parametrize("case", [
+    ([3, 5, 2, 7, 4], [1, 3, 17, 5, 2, 1], [1, 9, 2, 33, 6, 1]),          # two halves, ragged ranks
+    ([6, 9], [1, 7, 1], [1, 12, 1]),                                        # one sweep
+    ([16, 32, 8], [1, 128, 100, 1], [1, 90, 128, 1]),                       # large ranks
+    ([8, 4, 16, 4, 8, 4], [1, 64, 128, 96, 128, 50, 1], [1, 100, 128, 77, 128, 33, 1]),
+])
+def test_inner_bf16_mfma(ttc, case):
+    """prec BF16 on BF16 cores: the steps on BF16 MFMA, against the oracle on
+    the unrounded inputs (the BF16 bound) and on the values the GPU holds
+    (the arithmetic bound above); also the order-10 rank-32 pair."""
+    modes, rx, ry = case
+    x, y = random_pair(78, modes, rx, ry)
+    for xx, yy in ((x, y), (C.gen_tt_np(C.SEED_PAIR10, 1, C.pair10_shapes()[0]),
+                            C.gen_tt_np(C.SEED_PAIR10, 2, C.pair10_shapes()[1]))):
+        xg, xs = to_gpu(xx, "bf16")
+        yg, ys = to_gpu(yy, "bf16")
+        z = float(ttc.tt_contract_inner(xg, yg, prec="bf16").item())
+        assert scalar_err(z, O.inner_lr(xs, ys), tt_norm(xs), tt_norm(ys)) <= ARITH_BF16_MFMA
+        assert scalar_err(z, O.inner_lr(xx, yy), tt_norm(xx), tt_norm(yy)) <= TOL["bf16"]
+
+
+def test_inner_bf16_prec_refusals(ttc):
+    x, y = random_pair(79, [4, 5, 3], [1, 3, 4, 1], [1, 2, 5, 1])
+    xf, _ = to_gpu(x, "f32")
+    yf, _ = to_gpu(y, "f32")
+    with pytest.raises(ttc.TTCError) as ei:
+        ttc.tt_contract_inner(xf, yf, prec="bf16")
+    assert ei.value.name == "TTC_ERR_UNSUPPORTED"
+    xw, yw = random_pair(79, [4, 5], [1, 130, 1], [1, 3, 1])
+    with pytest.raises(ttc.TTCError) as ei:
+        ttc.tt_contract_inner(to_gpu(xw, "bf16")[0], to_gpu(yw, "bf16")[0], prec="bf16")
+    assert ei.value.name == "TTC_ERR_UNSUPPORTED"
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
 def test_inner_integer_cores_bit_exact(ttc, dtype):
     s = C.TTShape([4, 8, 3, 5, 6], [1, 5, 7, 3, 4, 1])
