@@ -52,7 +52,7 @@
 extern "C" {
 #endif
 
-#define TTC_ABI_VERSION 1
+#define TTC_ABI_VERSION 2
 #define TTC_MAX_ORDER 32 /* largest TT order accepted by single-pair calls */
 
 typedef enum {
@@ -174,6 +174,8 @@ ttc_status tt_contract_inner_noalloc(const ttc_tt* x, const ttc_tt* y, ttc_prec 
  * Prefix: K = W_k (R_k x P_k).  Suffix: K = V_k.  All: the scalar <X, Y>.
  *
  * modes / n_modes: host array of 0-based positions (any order, no repeats).
+ * prec: as for tt_contract_inner (BF16: BF16 cores, every rank <= 128, the
+ *       sweep on BF16 MFMA); the output forms are FP32 either way.
  * form: JUNCTION writes K (row-major, FP64 for FP64 inputs, FP32 otherwise)
  *       to out_junction; NATURAL_TT writes the cores of the natural-order TT
  *       into out_tt (shapes from the query; FP64 or FP32); DENSE writes the
@@ -192,11 +194,11 @@ ttc_status tt_contract_inner_noalloc(const ttc_tt* x, const ttc_tt* y, ttc_prec 
  * the output element count and the scratch size.
  * ------------------------------------------------------------------------ */
 ttc_status tt_contract_modes_query(const ttc_tt* x, const ttc_tt* y, const int32_t* modes,
-                                   int32_t n_modes, ttc_form form, int32_t* out_order,
-                                   int32_t* out_modes, int32_t* out_ranks, int64_t* out_elems,
-                                   size_t* ws_bytes);
+                                   int32_t n_modes, ttc_form form, ttc_prec prec,
+                                   int32_t* out_order, int32_t* out_modes, int32_t* out_ranks,
+                                   int64_t* out_elems, size_t* ws_bytes);
 ttc_status tt_contract_modes(const ttc_tt* x, const ttc_tt* y, const int32_t* modes,
-                             int32_t n_modes, ttc_form form, void* out_junction,
+                             int32_t n_modes, ttc_form form, ttc_prec prec, void* out_junction,
                              const ttc_tt* out_tt, void* out_dense, double* out_scalar,
                              void* d_ws, size_t ws_bytes, void* stream);
 

@@ -52,9 +52,9 @@ def _declare(lib):
         "tt_contract_inner_query": (c_int32, [P(TT), P(TT), c_int32, P(c_size_t)]),
         "tt_contract_inner": (c_int32, [P(TT), P(TT), c_int32, c_void_p, c_void_p, c_size_t, c_void_p]),
         "tt_contract_inner_noalloc": (c_int32, [P(TT), P(TT), c_int32, c_void_p, c_void_p]),
-        "tt_contract_modes_query": (c_int32, [P(TT), P(TT), P(c_int32), c_int32, c_int32, P(c_int32),
+        "tt_contract_modes_query": (c_int32, [P(TT), P(TT), P(c_int32), c_int32, c_int32, c_int32, P(c_int32),
                                               P(c_int32), P(c_int32), P(c_int64), P(c_size_t)]),
-        "tt_contract_modes": (c_int32, [P(TT), P(TT), P(c_int32), c_int32, c_int32, c_void_p, P(TT),
+        "tt_contract_modes": (c_int32, [P(TT), P(TT), P(c_int32), c_int32, c_int32, c_int32, c_void_p, P(TT),
                                         c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
         "tt_mode_n_product": (c_int32, [P(TT), c_int32, P(c_int32), P(c_void_p), P(c_int32), P(TT), c_void_p]),
         "ttm_apply_query": (c_int32, [P(TTM), P(TT), P(c_int32), P(c_int64)]),

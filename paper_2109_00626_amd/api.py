@@ -166,7 +166,7 @@ def tt_round(x, eps: float = 0.0, max_rank: int = 0):
     return [bufs[k][: r[k] * dx.modes[k] * r[k + 1]].view(r[k], dx.modes[k], r[k + 1]) for k in range(n)]
 
 
-def tt_contract_modes_query(x, y, modes, form: str = "junction"):
+def tt_contract_modes_query(x, y, modes, form: str = "junction", prec: str = "auto"):
     dx, dy = TTDesc(x, "x"), TTDesc(y, "y")
     m = _i32(modes)
     order = c_int32(0)
@@ -175,44 +175,45 @@ def tt_contract_modes_query(x, y, modes, form: str = "junction"):
     orr = (c_int32 * (2 * N + 3))()
     elems = c_int64(0)
     need = c_size_t(0)
-    _check(_lib.tt_contract_modes_query(dx.ref, dy.ref, m, len(modes), _abi.FORM[form], byref(order), om, orr,
-                                        byref(elems), byref(need)))
+    _check(_lib.tt_contract_modes_query(dx.ref, dy.ref, m, len(modes), _abi.FORM[form], _abi.PREC[prec],
+                                        byref(order), om, orr, byref(elems), byref(need)))
     n = order.value
     return {"order": n, "modes": list(om[:n]), "ranks": list(orr[: n + 1]) if form != "junction" else list(orr[:2]),
             "elems": elems.value, "ws": need.value}
 
 
-def tt_contract_modes(x, y, modes, form: str = "junction"):
+def tt_contract_modes(x, y, modes, form: str = "junction", prec: str = "auto"):
     """Contraction over shared positions `modes` (0-based).  Returns the
     scalar when every position is contracted; else the junction matrix K,
-    the list of natural-order cores, or the dense tensor."""
+    the list of natural-order cores, or the dense tensor.  prec "bf16" (BF16
+    cores): the sweep on BF16 MFMA."""
     dx, dy = TTDesc(x, "x"), TTDesc(y, "y")
-    q = tt_contract_modes_query(x, y, modes, form)
+    q = tt_contract_modes_query(x, y, modes, form, prec)
     dev = dx.device
     cdt = _comp_dtype(dx.dtype)
     ws = _ws(q["ws"], dev)
     m = _i32(modes)
-    f = _abi.FORM[form]
+    f, p = _abi.FORM[form], _abi.PREC[prec]
     st = _stream(dev)
     if len(set(int(v) for v in modes)) == len(x) and q["order"] == 0:
         out = torch.empty((), dtype=torch.float64, device=dev)
-        _check(_lib.tt_contract_modes(dx.ref, dy.ref, m, len(modes), f, None, None, None, _ptr(out), _ptr(ws),
+        _check(_lib.tt_contract_modes(dx.ref, dy.ref, m, len(modes), f, p, None, None, None, _ptr(out), _ptr(ws),
                                       q["ws"], st))
         return out
     if form == "junction":
         K = torch.empty(q["ranks"][0], q["ranks"][1], dtype=cdt, device=dev)
-        _check(_lib.tt_contract_modes(dx.ref, dy.ref, m, len(modes), f, _ptr(K), None, None, None, _ptr(ws),
+        _check(_lib.tt_contract_modes(dx.ref, dy.ref, m, len(modes), f, p, _ptr(K), None, None, None, _ptr(ws),
                                       q["ws"], st))
         return K
     if form == "natural":
         md, rk = q["modes"], q["ranks"]
         cores = [torch.empty(rk[k], md[k], rk[k + 1], dtype=cdt, device=dev) for k in range(q["order"])]
         od = TTDesc(cores, "out")
-        _check(_lib.tt_contract_modes(dx.ref, dy.ref, m, len(modes), f, None, od.ref, None, None, _ptr(ws),
+        _check(_lib.tt_contract_modes(dx.ref, dy.ref, m, len(modes), f, p, None, od.ref, None, None, _ptr(ws),
                                       q["ws"], st))
         return cores
     Z = torch.empty(*q["modes"], dtype=cdt, device=dev)
-    _check(_lib.tt_contract_modes(dx.ref, dy.ref, m, len(modes), f, None, None, _ptr(Z), None, _ptr(ws), q["ws"],
+    _check(_lib.tt_contract_modes(dx.ref, dy.ref, m, len(modes), f, p, None, None, _ptr(Z), None, _ptr(ws), q["ws"],
                                   st))
     return Z
 

@@ -265,7 +265,7 @@ bool lds_path(const ttc_tt* x, const ttc_tt* y) {
 // Runs the junction sweep (prefix: W_k left to right; suffix: V_k right to left)
 // into `kout` (compute type).
 ttc_status run_junction(const ttc_tt* x, const ttc_tt* y, BlockKind kind, int k, void* kout, Arena& ws,
-                        size_t ws_bytes, bool sizing, hipStream_t s) {
+                        size_t ws_bytes, bool sizing, hipStream_t s, bool m16 = false) {
   if (lds_path(x, y)) {
     // one workgroup, interface in LDS; a prefix runs on the reversed block
     PairLdsArgs pa;
@@ -282,6 +282,7 @@ ttc_status run_junction(const ttc_tt* x, const ttc_tt* y, BlockKind kind, int k,
     if (sizing) return TTC_OK;
     if (ws.off > ws_bytes) return fail(TTC_ERR_WORKSPACE, "workspace too small");
     pa.side[0].out = reinterpret_cast<float*>(kout);
+    pa.m16 = m16;
     if (kind == BK_PREFIX) TTC_HIP(launch_core_reverse(ra, s));
     TTC_HIP(launch_pair_lds(x->dtype, pa, 1, s));
     return TTC_OK;
@@ -502,9 +503,10 @@ ttc_status tt_contract_inner(const ttc_tt* x, const ttc_tt* y, ttc_prec prec, do
 }
 
 ttc_status tt_contract_modes_query(const ttc_tt* x, const ttc_tt* y, const int32_t* modes, int32_t n_modes,
-                                   ttc_form form, int32_t* out_order, int32_t* out_modes, int32_t* out_ranks,
-                                   int64_t* out_elems, size_t* ws_bytes) {
+                                   ttc_form form, ttc_prec prec, int32_t* out_order, int32_t* out_modes,
+                                   int32_t* out_ranks, int64_t* out_elems, size_t* ws_bytes) {
   TTC_TRY(check_pair(x, y));
+  TTC_TRY(check_inner_prec(x, y, prec));
   BlockKind kind;
   int k;
   TTC_TRY(classify(x->order, modes, n_modes, &kind, &k));
@@ -554,12 +556,13 @@ ttc_status tt_contract_modes_query(const ttc_tt* x, const ttc_tt* y, const int32
 }
 
 ttc_status tt_contract_modes(const ttc_tt* x, const ttc_tt* y, const int32_t* modes, int32_t n_modes,
-                             ttc_form form, void* out_junction, const ttc_tt* out_tt, void* out_dense,
-                             double* out_scalar, void* d_ws, size_t ws_bytes, void* stream) {
+                             ttc_form form, ttc_prec prec, void* out_junction, const ttc_tt* out_tt,
+                             void* out_dense, double* out_scalar, void* d_ws, size_t ws_bytes, void* stream) {
   size_t need = 0;
   int32_t order = 0;
   int64_t elems = 0;
-  TTC_TRY(tt_contract_modes_query(x, y, modes, n_modes, form, &order, nullptr, nullptr, &elems, &need));
+  TTC_TRY(tt_contract_modes_query(x, y, modes, n_modes, form, prec, &order, nullptr, nullptr, &elems, &need));
+  const bool m16 = prec == TTC_PREC_BF16;
   if (need > ws_bytes) return fail(TTC_ERR_WORKSPACE, "workspace smaller than tt_contract_modes_query size");
   if (need && !d_ws) return fail(TTC_ERR_NULL, "d_ws is NULL");
   BlockKind kind;
@@ -572,7 +575,7 @@ ttc_status tt_contract_modes(const ttc_tt* x, const ttc_tt* y, const int32_t* mo
     if (!out_scalar) return fail(TTC_ERR_NULL, "out_scalar is NULL (every position contracted)");
     TTC_TRY(ensure_init());
     Arena a(d_ws);
-    return run_inner(x, y, out_scalar, a, ws_bytes, false, s);
+    return run_inner(x, y, out_scalar, a, ws_bytes, false, s, m16);
   }
   std::vector<int> nm, nr;
   natural_shape(x, y, kind, k, &nm, &nr);
@@ -580,7 +583,7 @@ ttc_status tt_contract_modes(const ttc_tt* x, const ttc_tt* y, const int32_t* mo
     if (!out_junction) return fail(TTC_ERR_NULL, "out_junction is NULL");
     TTC_TRY(ensure_init());
     Arena a(d_ws);
-    return run_junction(x, y, kind, k, out_junction, a, ws_bytes, false, s);
+    return run_junction(x, y, kind, k, out_junction, a, ws_bytes, false, s, m16);
   }
   if (form == TTC_NATURAL_TT) TTC_TRY(check_out_tt(out_tt, nm, nr, cdt));
   if (form == TTC_DENSE) {
@@ -591,7 +594,7 @@ ttc_status tt_contract_modes(const ttc_tt* x, const ttc_tt* y, const int32_t* mo
   TTC_TRY(ensure_init());
   Arena a(d_ws);
   void* K = a.take((size_t)x->ranks[k] * y->ranks[k] * cs);
-  TTC_TRY(run_junction(x, y, kind, k, K, a, ws_bytes, false, s));
+  TTC_TRY(run_junction(x, y, kind, k, K, a, ws_bytes, false, s, m16));
   std::vector<void*> cores(nm.size());
   if (form == TTC_NATURAL_TT) {
     for (size_t m = 0; m < nm.size(); ++m) cores[m] = out_tt->cores[m];

@@ -64,15 +64,22 @@ int main() {
   int32_t order = 0, om[16], orr[17];
   int64_t elems = 0;
   for (int f = 0; f < 3; ++f) {
-    expect("modes prefix", tt_contract_modes_query(&x.d, &y.d, pre, 2, (ttc_form)f, &order, om, orr, &elems, &ws),
+    expect("modes prefix",
+           tt_contract_modes_query(&x.d, &y.d, pre, 2, (ttc_form)f, TTC_PREC_AUTO, &order, om, orr, &elems, &ws),
            TTC_OK);
-    expect("modes suffix", tt_contract_modes_query(&x.d, &y.d, suf, 2, (ttc_form)f, &order, om, orr, &elems, &ws),
+    expect("modes suffix",
+           tt_contract_modes_query(&x.d, &y.d, suf, 2, (ttc_form)f, TTC_PREC_AUTO, &order, om, orr, &elems, &ws),
            TTC_OK);
   }
-  expect("modes middle", tt_contract_modes_query(&x.d, &y.d, mid, 1, TTC_JUNCTION, &order, om, orr, &elems, &ws),
+  expect("modes middle",
+         tt_contract_modes_query(&x.d, &y.d, mid, 1, TTC_JUNCTION, TTC_PREC_AUTO, &order, om, orr, &elems, &ws),
          TTC_ERR_UNSUPPORTED);
-  expect("modes repeat", tt_contract_modes_query(&x.d, &y.d, rep, 2, TTC_JUNCTION, &order, om, orr, &elems, &ws),
+  expect("modes repeat",
+         tt_contract_modes_query(&x.d, &y.d, rep, 2, TTC_JUNCTION, TTC_PREC_AUTO, &order, om, orr, &elems, &ws),
          TTC_ERR_MODE);
+  expect("modes bf16 prec on fp32",
+         tt_contract_modes_query(&x.d, &y.d, pre, 2, TTC_JUNCTION, TTC_PREC_BF16, &order, om, orr, &elems, &ws),
+         TTC_ERR_UNSUPPORTED);
   // contractions at any positions, every form
   Tt a({3, 4, 5, 2}, {1, 2, 3, 2, 1}), b({3, 5, 4}, {1, 2, 3, 1});
   const int32_t xm[1] = {2}, ym[1] = {1}, xm2[2] = {0, 2}, ym2[2] = {0, 1};

@@ -45,7 +45,7 @@ def test_exports_every_declared_symbol(lib, abi):
     for n in names:
         assert hasattr(lib, n), n
     assert set(names) == set(abi.EXPORTED)
-    assert lib.ttc_abi_version() == 1
+    assert lib.ttc_abi_version() == 2
     assert b"gfx950" in lib.ttc_version()
 
 
@@ -110,15 +110,15 @@ def test_inner_validation(lib, abi):
     assert status_name(abi, lib.tt_contract_inner_query(byref(zero.s), byref(y.s), 0, byref(need))) == "TTC_ERR_SHAPE"
 
 
-def _modes_query(lib, abi, x, y, modes, form):
+def _modes_query(lib, abi, x, y, modes, form, prec=0):
     m = (c_int32 * len(modes))(*modes)
     order = c_int32(0)
     om = (c_int32 * 64)()
     orr = (c_int32 * 65)()
     el = c_int64(0)
     ws = c_size_t(0)
-    st = lib.tt_contract_modes_query(byref(x.s), byref(y.s), m, len(modes), form, byref(order), om, orr, byref(el),
-                                     byref(ws))
+    st = lib.tt_contract_modes_query(byref(x.s), byref(y.s), m, len(modes), form, prec, byref(order), om, orr,
+                                     byref(el), byref(ws))
     return st, order.value, list(om[:order.value]), list(orr[:order.value + 1]), el.value
 
 

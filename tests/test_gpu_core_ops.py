@@ -221,6 +221,27 @@ def test_modes_ragged_prefix_suffix(ttc, modes, dtype):
     assert rel_err(Z, O.contract_dense(*ref, modes)) <= tol
 
 
+@pytest.mark.parametrize("modes", [[0], [0, 1, 2], [3], [1, 2, 3], [0, 1, 2, 3]])
+def test_modes_bf16_mfma(ttc, modes):
+    """prec BF16 on BF16 cores: the junction sweep on BF16 MFMA, every form,
+    against the oracle on the unrounded inputs (BF16 bound) and on the
+    values the GPU holds (the BF16-MFMA arithmetic bound)."""
+    x, y = random_pair(92, [3, 5, 2, 4], [1, 3, 6, 2, 1], [1, 2, 5, 7, 1])
+    xg, xs = to_gpu(x, "bf16")
+    yg, ys = to_gpu(y, "bf16")
+    if len(modes) == 4:
+        z = ttc.tt_contract_modes(xg, yg, modes, "junction", prec="bf16").item()
+        assert scalar_err(z, O.inner_lr(xs, ys), tt_norm(xs), tt_norm(ys)) <= ARITH_BF16_MFMA
+        return
+    for ref, tol in (((x, y), TOL["bf16"]), ((xs, ys), ARITH_BF16_MFMA)):
+        K = to_np(ttc.tt_contract_modes(xg, yg, modes, "junction", prec="bf16"))
+        assert rel_err(K, O.contract_junction(*ref, modes)[2]) <= tol
+        nat = [to_np(t) for t in ttc.tt_contract_modes(xg, yg, modes, "natural", prec="bf16")]
+        assert max_core_rel(nat, O.contract_natural(*ref, modes)) <= tol
+        Z = to_np(ttc.tt_contract_modes(xg, yg, modes, "dense", prec="bf16"))
+        assert rel_err(Z, O.contract_dense(*ref, modes)) <= tol
+
+
 @pytest.mark.parametrize("modes", [[0], [1], [0, 1]])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_modes_order2(ttc, modes, dtype):
