@@ -585,6 +585,33 @@ def main():
             Q = int(np.prod(sh.modes[:k])) if k > 0 else 1
             fl += 2.0 * P * Q * sh.cols[k] * sh.ranks[k] * sh.modes[k] * sh.ranks[k + 1]
         beside["layer4_cores_f32_fwd_TFLOPs"] = round(fl / (beside["layer4_cores_f32_fwd_ms"] * 1e-3) / 1e12, 2)
+        # forward + backward executes three products of the forward's size per
+        # core (forward, input gradient, core gradient)
+        beside["layer4_cores_f32_fwd_bwd_TFLOPs"] = round(3 * fl / (beside["layer4_cores_f32_fwd_bwd_ms"] * 1e-3) / 1e12,
+                                                         2)
+
+    # the TT-method kernels against their own rooflines (the step's dominant
+    # kernel above is the layer's dense-schedule GEMM)
+    if not args.no_beside:
+        mr = {}
+
+        def hbm(name, kernel, gbs):
+            mr[name] = {"kernel": kernel, "bound": "hbm", "achieved_GBs": round(gbs, 1),
+                        "frac": round(gbs / PEAK["hbm_GBs"], 4)}
+
+        if "batch_fp32" in beside:
+            hbm("batch_fp32", "batch_lds_kernel (FP32 cores, FP32 MFMA steps)", beside["batch_fp32"]["GBs"])
+        if "batch_bf16" in beside:
+            hbm("batch_bf16", "batch_lds_kernel (BF16 cores, " + beside["batch_bf16"]["schedule"]["mode"] + ")",
+                beside["batch_bf16"]["GBs"])
+        if "mpo8" in parts:
+            hbm("mpo8", "mpo_stream_kernel (BF16 MFMA, write stream)", parts_out["mpo8"]["GBs"])
+        if "layer4_cores_f32_fwd_bwd_TFLOPs" in beside:
+            t = beside["layer4_cores_f32_fwd_bwd_TFLOPs"]
+            mr["layer4_cores_fwd_bwd"] = {"kernel": "gemm_kernel (FP32 MFMA), one product per core and direction",
+                                          "bound": "mfma", "achieved_TFLOPs": t,
+                                          "frac": round(t / PEAK["fp32_TFLOPs"], 4)}
+        beside["method_rooflines"] = mr
 
     if not args.no_beside:
         beside["example2"] = example2_gpu(ttc)
