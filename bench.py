@@ -49,7 +49,69 @@ def parse():
                     help="arithmetic of the layer part (bf16: the BF16-MFMA option as the timed part, for profiling it)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB mebibytes five times (counter calibration)")
+    ap.add_argument("--trace-batch", action="store_true",
+                    help="only run the batch once with per-step clocks and print where its time goes")
     return ap.parse_args()
+
+
+def trace_batch(ttc, batch_dtype):
+    """One traced run of the 4096-pair batch (tt_batch_run_traced): each
+    step's duration in shader cycles against its MFMA count (4 RT I QT
+    (KC + PT) for the step's padded tiles: RT output row tiles, I mode
+    indices, QT 16-wide slices of the second contracted bond, KC and PT the
+    16-wide chunks of the first contracted bond and of the output columns),
+    a least-squares fit cycles = fixed + per_mfma * MFMAs, and the cycles by
+    MFMA-count range and by KC + PT."""
+    import numpy as np
+    import torch
+    from ttgen import configs as C
+    p16 = lambda n: (n + 15) // 16 * 16
+
+    def y_first(rp, rn, pp, pn):
+        return p16(pp) * p16(rn) * (p16(pn) + p16(rp)) < p16(rp) * p16(pn) * (p16(rn) + p16(pp))
+
+    shapes = C.batch_pair_shapes(C.SEED_BATCH, 4096)
+    pairs = C.gen_batch_torch(C.SEED_BATCH, shapes, "cuda", torch.bfloat16 if batch_dtype == "bf16" else torch.float32)
+    plan = ttc.BatchPlan(pairs)
+    inner, junc = plan.outputs()
+    plan.run(inner, junc)
+    torch.cuda.synchronize()
+    _, _, per, steps = plan.run_traced(inner, junc)
+    per, steps = per.numpy(), steps.numpy()
+    mf, cyc, kp = [], [], []
+    tail = 0.0
+    for p, (sx, sy) in enumerate(shapes):
+        n, prev = sx.order, per[p, 0]
+        for j in range(n - 1):
+            k = n - 1 - j
+            rp, rn, pp, pn = sx.ranks[k], sx.ranks[k + 1], sy.ranks[k], sy.ranks[k + 1]
+            ma, ka, nb, kb = (pp, pn, rp, rn) if y_first(rp, rn, pp, pn) else (rp, rn, pp, pn)
+            mf.append(4 * (p16(ma) // 16) * sx.modes[k] * (p16(kb) // 16) * (p16(ka) // 16 + p16(nb) // 16))
+            cyc.append(steps[p, j] - prev)
+            kp.append(p16(ka) // 16 + p16(nb) // 16)
+            prev = steps[p, j]
+        tail += per[p, 1] - prev
+    mf, cyc, kp = np.array(mf, float), np.array(cyc, float), np.array(kp)
+    fit = np.linalg.lstsq(np.vstack([np.ones_like(mf), mf]).T, cyc, rcond=None)[0]
+    wg = {}
+    for p in range(len(shapes)):
+        wg[int(per[p, 2])] = wg.get(int(per[p, 2]), 0.0) + float(per[p, 1] - per[p, 0])
+    ranges = {}
+    for lo, hi in ((0, 256), (256, 1024), (1024, 4096), (4096, 16384), (16384, 1 << 40)):
+        m = (mf >= lo) & (mf < hi)
+        if m.any():
+            ranges[f"[{lo},{hi})"] = {"steps": int(m.sum()), "Gcycles": round(cyc[m].sum() / 1e9, 3),
+                                      "cycles_per_mfma": round(cyc[m].sum() / mf[m].sum(), 1)}
+    by_kp = {int(v): {"steps": int((kp == v).sum()),
+                      "cycles_per_mfma": round(cyc[kp == v].sum() / mf[kp == v].sum(), 1)} for v in np.unique(kp)}
+    print(json.dumps({"batch_trace": {"dtype": batch_dtype, "schedule": plan.config, "steps": len(mf),
+                                      "fit_fixed_cycles": round(fit[0]), "fit_cycles_per_mfma": round(fit[1], 2),
+                                      "step_Gcycles": round(cyc.sum() / 1e9, 3),
+                                      "fixed_share": round(fit[0] * len(mf) / cyc.sum(), 3),
+                                      "final_products_Gcycles": round(tail / 1e9, 3),
+                                      "per_workgroup_Mcycles": {"mean": round(np.mean(list(wg.values())) / 1e6, 3),
+                                                                "max": round(max(wg.values()) / 1e6, 3)},
+                                      "by_mfma_count": ranges, "by_KC_plus_PT": by_kp}}))
 
 
 # ------------------------------------------------------------- HBM traffic
@@ -403,6 +465,10 @@ def main():
         return
 
     import paper_2109_00626_amd as ttc
+
+    if args.trace_batch:
+        trace_batch(ttc, args.batch_dtype)
+        return
 
     parts = [p for p in args.parts.split(",") if p]
     W = setup(parts, args.batch_dtype)
