@@ -622,24 +622,25 @@ def main():
         # GEMM per core, 4x the FLOPs of the dense schedule on this shape;
         # forward + backward keep the forward's intermediates for the
         # backward (schedule cores_saved, one workspace for both calls)
-        cws = torch.empty(ttc.ttm_apply_dense_query(d["w"], 8192, "f32", "cores_saved", backward=True),
-                          dtype=torch.uint8, device=d["X"].device)
+        cws = torch.empty(max(ttc.ttm_apply_dense_query(d["w"], 8192, p, "cores_saved", backward=True)
+                              for p in ("f32", "bf16")), dtype=torch.uint8, device=d["X"].device)
 
-        def cores(bwd):
+        def cores(bwd, prec):
             if not bwd:
-                ttc.ttm_apply_dense(d["w"], d["X"], sched="cores")
+                ttc.ttm_apply_dense(d["w"], d["X"], sched="cores", prec=prec)
                 return
-            Y = ttc.ttm_apply_dense(d["w"], d["X"], sched="cores_saved", ws=cws)
+            Y = ttc.ttm_apply_dense(d["w"], d["X"], sched="cores_saved", prec=prec, ws=cws)
             _, dY = ttc.ttc_mse_loss(Y, d["T"])
-            ttc.ttm_apply_dense_bwd(d["w"], d["X"], dY, sched="cores_saved", ws=cws)
+            ttc.ttm_apply_dense_bwd(d["w"], d["X"], dY, sched="cores_saved", prec=prec, ws=cws)
 
-        for bwd, key in ((False, "layer4_cores_f32_fwd_ms"), (True, "layer4_cores_f32_fwd_bwd_ms")):
-            cores(bwd)
+        for bwd, prec, key in ((False, "f32", "layer4_cores_f32_fwd_ms"), (True, "f32", "layer4_cores_f32_fwd_bwd_ms"),
+                               (True, "bf16", "layer4_cores_bf16_fwd_bwd_ms")):
+            cores(bwd, prec)
             torch.cuda.synchronize()
             a = torch.cuda.Event(enable_timing=True)
             b = torch.cuda.Event(enable_timing=True)
             a.record(stream)
-            cores(bwd)
+            cores(bwd, prec)
             b.record(stream)
             torch.cuda.synchronize()
             beside[key] = round(a.elapsed_time(b), 4)
@@ -677,6 +678,11 @@ def main():
             mr["layer4_cores_fwd_bwd"] = {"kernel": "gemm_kernel (FP32 MFMA), one product per core and direction",
                                           "bound": "mfma", "achieved_TFLOPs": t,
                                           "frac": round(t / PEAK["fp32_TFLOPs"], 4)}
+            t16 = beside["layer4_cores_f32_fwd_bwd_TFLOPs"] * beside["layer4_cores_f32_fwd_bwd_ms"] / \
+                beside["layer4_cores_bf16_fwd_bwd_ms"]
+            mr["layer4_cores_bf16_fwd_bwd"] = {"kernel": "gemm_kernel (BF16 MFMA, FP32 operands rounded while staged)",
+                                               "bound": "mfma", "achieved_TFLOPs": round(t16, 2),
+                                               "frac": round(t16 / PEAK["bf16_TFLOPs"], 4)}
         beside["method_rooflines"] = mr
 
     if not args.no_beside:
