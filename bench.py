@@ -662,9 +662,9 @@ def main():
     if not args.no_beside:
         mr = {}
 
-        def hbm(name, kernel, gbs):
+        def hbm(name, kernel, gbs, traffic=None):
             mr[name] = {"kernel": kernel, "bound": "hbm", "achieved_GBs": round(gbs, 1),
-                        "frac": round(gbs / PEAK["hbm_GBs"], 4)}
+                        "frac": round(gbs / PEAK["hbm_GBs"], 4), "traffic": traffic}
 
         if "batch_fp32" in beside:
             hbm("batch_fp32", "batch_lds_kernel (FP32 cores, FP32 MFMA steps)", beside["batch_fp32"]["GBs"])
@@ -672,7 +672,8 @@ def main():
             hbm("batch_bf16", "batch_lds_kernel (BF16 cores, " + beside["batch_bf16"]["schedule"]["mode"] + ")",
                 beside["batch_bf16"]["GBs"])
         if "mpo8" in parts:
-            hbm("mpo8", "mpo_stream_kernel (BF16 MFMA, write stream)", parts_out["mpo8"]["GBs"])
+            hbm("mpo8", "mpo16_kernel (BF16 MFMA, write stream)", parts_out["mpo8"]["GBs"],
+                recorded_traffic("mpo16_kernel"))
         if "layer4_cores_f32_fwd_bwd_TFLOPs" in beside:
             t = beside["layer4_cores_f32_fwd_bwd_TFLOPs"]
             mr["layer4_cores_fwd_bwd"] = {"kernel": "gemm_kernel (FP32 MFMA), one product per core and direction",

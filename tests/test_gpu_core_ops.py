@@ -394,6 +394,29 @@ def test_mpo_tiles_and_tails(ttc, dtype):
     assert max_core_rel(out, want) <= TOL[dtype]
 
 
+@pytest.mark.parametrize("case", [
+    # r' tiles 7 (r1 = 100), J = 50 (two K steps), I = 13 (a ragged chunk of
+    # mode indices), r0 = 100 (a ragged group of waves), r1 = 1 (scalar stores)
+    (C.TTShape([13, 3], [1, 5, 1], [50, 7]), C.TTShape([50, 7], [1, 100, 1])),
+    # a1 = 200: the staged W chunk shrinks to fit; a ragged a' tile
+    (C.TTShape([5, 2], [1, 200, 1], [64, 3]), C.TTShape([64, 3], [1, 8, 1])),
+    # r1 = 130 and J = 70: beyond the register fragments (the LDS kernel)
+    (C.TTShape([3, 2], [1, 3, 1], [70, 4]), C.TTShape([70, 4], [1, 130, 1])),
+])
+def test_mpo_bf16_shapes(ttc, case):
+    """BF16 MPO x TT across the limits of the register-fragment kernel and
+    the fallback beyond them: every core against the oracle on the rounded
+    inputs (FP32 bound) and on the unrounded ones (BF16 bound)."""
+    sw, sv = case
+    w = C.gen_tt_np(44, 1, sw)
+    v = C.gen_tt_np(44, 2, sv)
+    wg, ws = to_gpu(w, "bf16")
+    vg, vs = to_gpu(v, "bf16")
+    out = [to_np(t) for t in ttc.ttm_apply(wg, vg)]
+    assert max_core_rel(out, O.mpo_tt(ws, vs)) <= TOL["f32"]
+    assert max_core_rel(out, O.mpo_tt(w, v)) <= TOL["bf16"]
+
+
 def test_mpo8_bf16_full(ttc):
     """Order-8 MPO (I = J = 32, rank 16) on an order-8 TT (mode 32, rank 64),
     BF16 inputs, FP32 output with ranks 1024.  Every core in full: the total
