@@ -71,14 +71,21 @@ struct Vec16<double> {
   typedef double type __attribute__((ext_vector_type(2)));
 };
 
-constexpr int kLiftUnroll = 4;
+#ifndef LIFT_UNROLL
+#define LIFT_UNROLL 1
+#endif
+constexpr int kLiftUnroll = LIFT_UNROLL;
 
 // The output cores as one stream of items (a run of `vec` consecutive
 // outputs of one line; 16 bytes when the line length allows).  A thread
 // takes kLiftUnroll items a grid stride apart and computes all of them
-// (issuing their source loads together) before it stores any, so one
-// load latency covers several stores.  Item ranges start at multiples of
-// 64, so a wave's items lie in one core and the core lookup is uniform.
+// (issuing their source loads together) before it stores any.  One item
+// per pass is the fastest: loads and stores share one completion counter,
+// so each pass's source loads also wait for the stores issued before them,
+// and more items per pass only lengthen that wait (natural-form output of
+// the order-10 pair, 204 MB: 34.5 us with one item, 39 with two, 44 with
+// four, 83 with eight).  Item ranges start at multiples of 64, so a wave's
+// items lie in one core and the core lookup is uniform.
 template <typename Tin, typename Tc>
 __global__ __launch_bounds__(256) void lift_kernel(LiftArgs a, long total_items) {
   constexpr int VW = 16 / sizeof(Tc);
@@ -173,7 +180,10 @@ __global__ __launch_bounds__(256) void dense_kernel(DenseArgs a) {
 }
 
 // Workgroups of the lift at most (a grid-stride loop covers the rest).
-const long kLiftGrid = 8192;
+#ifndef LIFT_GRID
+#define LIFT_GRID 8192
+#endif
+const long kLiftGrid = LIFT_GRID;
 
 hipError_t launch_lift(ttc_dtype dt, const LiftArgs& in, int total_lines, hipStream_t s) {
   if (total_lines <= 0) return hipSuccess;
