@@ -667,7 +667,9 @@ def main():
                         "frac": round(gbs / PEAK["hbm_GBs"], 4), "traffic": traffic}
 
         if "batch_fp32" in beside:
-            hbm("batch_fp32", "batch_lds_kernel (FP32 cores, FP32 MFMA steps)", beside["batch_fp32"]["GBs"])
+            bc = W["batch"]["plan"].config
+            hbm("batch_fp32", "batch_lds_kernel (FP32 cores, FP32 MFMA steps)", beside["batch_fp32"]["GBs"],
+                recorded_traffic(f"batch_lds_kernel_inplace/{bc['threads']}") if bc["mode"] == "lds1" else None)
         if "batch_bf16" in beside:
             hbm("batch_bf16", "batch_lds_kernel (BF16 cores, " + beside["batch_bf16"]["schedule"]["mode"] + ")",
                 beside["batch_bf16"]["GBs"])
