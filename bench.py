@@ -657,6 +657,32 @@ def main():
         beside["layer4_cores_f32_fwd_bwd_TFLOPs"] = round(3 * fl / (beside["layer4_cores_f32_fwd_bwd_ms"] * 1e-3) / 1e12,
                                                          2)
 
+    # a middle block of the order-10 pair (X's modes 4-7 with Y's, eq. (8)
+    # once per pair): the two-sided transfer, executed FLOPs of its products
+    if not args.no_beside and "pair10" in W:
+        d = W["pair10"]
+        mid = [3, 4, 5, 6]
+        f = lambda: ttc.tt_contract_pairs(d["x"], d["y"], mid, mid, "junction")
+        for _ in range(3):
+            f()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(20):
+            f()
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / 20
+        sx, sy = d["sx"], d["sy"]
+        a0, g0 = sx.ranks[mid[0]], sy.ranks[mid[0]]
+        fl = 2.0 * a0 * g0 * sx.ranks[mid[0] + 1] * sy.ranks[mid[0] + 1] * sx.modes[mid[0]]
+        for k in mid[1:]:
+            ka1, kg1, nm, kb, kd = sx.ranks[k], sy.ranks[k], sx.modes[k], sx.ranks[k + 1], sy.ranks[k + 1]
+            fl += 2.0 * a0 * g0 * (kg1 * nm * kb * ka1 + kb * kd * kg1 * nm)
+        beside["pairs_middle_fp32"] = {"modes": [m + 1 for m in mid], "ms": round(ms, 4),
+                                       "GFLOP": round(fl / 1e9, 3), "TFLOPs": round(fl / (ms * 1e-3) / 1e12, 2)}
+
     # the TT-method kernels against their own rooflines (the step's dominant
     # kernel above is the layer's dense-schedule GEMM)
     if not args.no_beside:
@@ -686,6 +712,10 @@ def main():
             mr["layer4_cores_bf16_fwd_bwd"] = {"kernel": "gemm_kernel (BF16 MFMA, FP32 operands rounded while staged)",
                                                "bound": "mfma", "achieved_TFLOPs": round(t16, 2),
                                                "frac": round(t16 / PEAK["bf16_TFLOPs"], 4)}
+        if "pairs_middle_fp32" in beside:
+            t = beside["pairs_middle_fp32"]["TFLOPs"]
+            mr["pairs_middle_fp32"] = {"kernel": "gemm_kernel batched over the transfer rows (FP32 MFMA), the whole call",
+                                       "bound": "mfma", "achieved_TFLOPs": t, "frac": round(t / PEAK["fp32_TFLOPs"], 4)}
         beside["method_rooflines"] = mr
 
     if not args.no_beside:

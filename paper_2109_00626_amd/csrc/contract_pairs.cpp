@@ -18,12 +18,13 @@
 #include <string>
 #include <vector>
 
-#include "ttc_internal.h"
+#include "ttc_layer.h"
 
 namespace ttc {
 ttc_status fail(ttc_status s, const std::string& msg);
 hipError_t launch_transfer_first(ttc_dtype dt, const void* gx, const void* gy, int ka, int kg, int n, int kb,
                                  int kd, void* E, hipStream_t s);
+hipError_t launch_widen(const void* src, float* dst, long n, hipStream_t s);
 hipError_t launch_transfer_step(ttc_dtype dt, const void* E, const void* gx, const void* gy, long rows, int ka1,
                                 int kg1, int n, int kb, int kd, void* F, void* Eout, hipStream_t s);
 }  // namespace ttc
@@ -75,6 +76,10 @@ struct PairsPlan {
   bool all = false;
   long rows = 1;          // ka * kg
   long e_max = 1, f_max = 1;
+  // FP32 / BF16 cores: the steps after the first pair are MFMA products
+  // (BF16 cores widened to FP32 first, exactly); FP64: per-entry FMA sums
+  bool mfma = false;
+  long gx_max = 0, gy_max = 0;
   int Q = 1;              // carried bond of the natural form
   std::vector<NatCore> nat;
   std::vector<int> nmodes, nranks;
@@ -125,6 +130,15 @@ ttc_status plan_pairs(const ttc_tt* x, const ttc_tt* y, const int32_t* xm, const
   }
   if (P->e_max > kMaxTransferElems || P->f_max > kMaxTransferElems)
     return fail(TTC_ERR_UNSUPPORTED, "transfer matrix of the blocks exceeds 2^28 elements");
+  // (the products are batched over the rows (a, g): at most 65535 of them)
+  P->mfma = x->dtype != TTC_F64 && n > 1 && P->rows <= 65535;
+  if (P->mfma) {
+    for (int l = 1; l < n; ++l) {
+      const int mx = P->a1 + l, my = P->b1 + l;
+      P->gx_max = std::max(P->gx_max, (long)x->ranks[mx] * x->modes[mx] * x->ranks[mx + 1]);
+      P->gy_max = std::max(P->gy_max, (long)y->ranks[my] * y->modes[my] * y->ranks[my + 1]);
+    }
+  }
   // natural form
   P->nat.clear();
   P->nmodes.clear();
@@ -195,6 +209,7 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct PairsWs {
   size_t e0 = 0, e1 = 0, f = 0, cores = 0, inner = 0, total = 0;
+  size_t gx = 0, gy = 0;  // MFMA steps on BF16 cores: the cores widened to FP32
   std::vector<size_t> core_off;
 };
 
@@ -213,6 +228,10 @@ ttc_status size_ws(const ttc_tt* x, const ttc_tt* y, const PairsPlan& P, ttc_for
     W->e0 = take(P.e_max * P.cs);
     W->e1 = take(P.e_max * P.cs);
     W->f = take(P.f_max * P.cs);
+    if (P.mfma && x->dtype == TTC_BF16) {
+      W->gx = take(P.gx_max * 4);
+      W->gy = take(P.gy_max * 4);
+    }
     if (form == TTC_DENSE) {
       W->core_off.clear();
       for (const auto& c : P.nat) W->core_off.push_back(take((size_t)c.d0 * c.n * c.d1 * P.cs));
@@ -316,8 +335,32 @@ ttc_status tt_contract_pairs(const ttc_tt* x, const ttc_tt* y, const int32_t* xm
                                y->ranks[P.b1 + 1], E, s));
   for (int l = 1; l < P.L; ++l) {
     const int mx = P.a1 + l, my = P.b1 + l;
-    CP_HIP(launch_transfer_step(dt, E, x->cores[mx], y->cores[my], P.rows, x->ranks[mx], y->ranks[my],
-                                x->modes[mx], x->ranks[mx + 1], y->ranks[my + 1], F, E2, s));
+    const int ka1 = x->ranks[mx], kg1 = y->ranks[my], nm = x->modes[mx], kb = x->ranks[mx + 1],
+              kd = y->ranks[my + 1];
+    if (!P.mfma) {
+      CP_HIP(launch_transfer_step(dt, E, x->cores[mx], y->cores[my], P.rows, ka1, kg1, nm, kb, kd, F, E2, s));
+      std::swap(E, E2);
+      continue;
+    }
+    // E holds [(a, g)][a'][g'] (rows x ka1 x kg1)
+    const float* gx = reinterpret_cast<const float*>(x->cores[mx]);
+    const float* gy = reinterpret_cast<const float*>(y->cores[my]);
+    if (dt == TTC_BF16) {
+      float* wx = reinterpret_cast<float*>(ws + W.gx);
+      float* wy = reinterpret_cast<float*>(ws + W.gy);
+      CP_HIP(launch_widen(x->cores[mx], wx, (long)ka1 * nm * kb, s));
+      CP_HIP(launch_widen(y->cores[my], wy, (long)kg1 * nm * kd, s));
+      gx = wx;
+      gy = wy;
+    }
+    // per row (a, g), one product each (batched over the rows):
+    //   F[row][g'][(i, b)] = sum_a' E[row][a'][g'] Gx[a'][(i, b)]
+    //   E'[row][b][d]      = sum_{(g', i)} F[row][(g', i)][b] Gy[(g', i)][d]
+    const long fr = (long)kg1 * nm * kb;
+    CP_TRY(gemm_f32_batched(false, reinterpret_cast<const float*>(E), kg1, (long)ka1 * kg1, false, gx, (long)nm * kb,
+                            0, reinterpret_cast<float*>(F), (long)nm * kb, fr, kg1, nm * kb, ka1, (int)P.rows, s));
+    CP_TRY(gemm_f32_batched(false, reinterpret_cast<const float*>(F), kb, fr, false, gy, kd, 0,
+                            reinterpret_cast<float*>(E2), kd, (long)kb * kd, kb, kd, kg1 * nm, (int)P.rows, s));
     std::swap(E, E2);
   }
   if (form == TTC_JUNCTION) {

@@ -190,6 +190,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 1 : 
   const int kbeg = blockIdx.y * kper;
   const int kend = min(g.K, kbeg + kper);
   const int nk = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
+  const float* const Ag = g.A + (long)blockIdx.z * g.sa;  // batch member (z = 0 unless batched)
+  const float* const Bg = g.B + (long)blockIdx.z * g.sb;
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = wave / S::WN, wn = wave % S::WN;
@@ -203,8 +205,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 1 : 
 
   f32x4 ra[LA], rb[LB];
   if (nk > 0) {
-    load_tile<BF16, A_KC, TM>(g.A, g.lda, m0, g.M, kbeg, kend, g.vec_a, ra);
-    load_tile<BF16, B_KC, TN>(g.B, g.ldb, n0, g.N, kbeg, kend, g.vec_b, rb);
+    load_tile<BF16, A_KC, TM>(Ag, g.lda, m0, g.M, kbeg, kend, g.vec_a, ra);
+    load_tile<BF16, B_KC, TN>(Bg, g.ldb, n0, g.N, kbeg, kend, g.vec_b, rb);
     store_tile<BF16, A_KC, TM>(As, ra);
     store_tile<BF16, B_KC, TN>(Bs, rb);
   }
@@ -213,8 +215,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 1 : 
     const int buf = kt & 1;
     if (kt + 1 < nk) {
       const int k0 = kbeg + (kt + 1) * BK;
-      load_tile<BF16, A_KC, TM>(g.A, g.lda, m0, g.M, k0, kend, g.vec_a, ra);
-      load_tile<BF16, B_KC, TN>(g.B, g.ldb, n0, g.N, k0, kend, g.vec_b, rb);
+      load_tile<BF16, A_KC, TM>(Ag, g.lda, m0, g.M, k0, kend, g.vec_a, ra);
+      load_tile<BF16, B_KC, TN>(Bg, g.ldb, n0, g.N, k0, kend, g.vec_b, rb);
     }
     if (!BF16) {
       const float* a_s = reinterpret_cast<const float*>(As) + buf * TA;
@@ -258,7 +260,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 1 : 
     }
     __syncthreads();
   }
-  float* C = g.splits > 1 ? g.slab + (long)blockIdx.y * g.M * g.N : g.C;
+  float* C = g.splits > 1 ? g.slab + (long)blockIdx.y * g.M * g.N : g.C + (long)blockIdx.z * g.sc;
   const long ldc = g.splits > 1 ? g.N : g.ldc;
   const float alpha = g.splits > 1 ? 1.f : g.alpha;
   if (g.mapped) {
@@ -572,7 +574,8 @@ static hipError_t gemm_launch(const GemmArgs& g, hipStream_t s) {
   });
   if (e != hipSuccess) return e;
   const int tiles = ((g.M + TM - 1) / TM) * ((g.N + TN - 1) / TN);
-  hipLaunchKernelGGL((gemm_kernel<A_KC, B_KC, BF16, TM, TN>), dim3(tiles, g.splits), dim3(256), lds, s, g);
+  hipLaunchKernelGGL((gemm_kernel<A_KC, B_KC, BF16, TM, TN>), dim3(tiles, g.splits, g.batch > 1 ? g.batch : 1),
+                     dim3(256), lds, s, g);
   return hipGetLastError();
 }
 

@@ -158,7 +158,8 @@ bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
 
 // One GEMM with split-K chosen to give the GPU enough workgroups.
 ttc_status gemm(bool a_kc, const float* A, long lda, bool b_kc, const float* B, long ldb, float* C, long ldc, int M,
-                int N, int K, bool bf16, float* slab, hipStream_t s, const IdxMap* map = nullptr) {
+                int N, int K, bool bf16, float* slab, hipStream_t s, const IdxMap* map = nullptr,
+                size_t slab_elems = kSlabElems) {
   GemmArgs g;
   std::memset(&g, 0, sizeof(g));
   if (map) {
@@ -183,14 +184,14 @@ ttc_status gemm(bool a_kc, const float* A, long lda, bool b_kc, const float* B, 
   const long tiles = (long)((M + tm - 1) / tm) * ((N + tn - 1) / tn);
   const int bk = gemm_bk(bf16);
   int splits = 1;
-  if (tiles < 512 && !map) {
+  if (tiles < 512 && !map && slab) {
     // about 1024 workgroups; at most 256 partial slabs (the reduction reads
     // every slab once per output element), 1024 for outputs of at most 64 K
     // elements
     const long cap = (long)M * N <= 65536 ? 1024L : 256L;
     long want = std::min(cap, (1024 + tiles - 1) / tiles);
     long by_k = K / (4L * bk);
-    long by_slab = (long)(kSlabElems / ((size_t)M * N));
+    long by_slab = (long)(slab_elems / ((size_t)M * N));
     splits = (int)std::max(1L, std::min(want, std::min(by_k, by_slab)));
   }
   g.splits = splits;
@@ -538,6 +539,41 @@ ttc_status check_common(const ttc_ttm* m, int64_t batch, ttc_prec prec, ttc_sche
 }
 
 }  // namespace
+
+namespace ttc {
+ttc_status gemm_f32(bool a_kc, const float* A, long lda, bool b_kc, const float* B, long ldb, float* C, long ldc,
+                    int M, int N, int K, float* slab, size_t slab_elems, hipStream_t s, const IdxMap* map) {
+  return gemm(a_kc, A, lda, b_kc, B, ldb, C, ldc, M, N, K, false, slab, s, map, slab_elems);
+}
+
+ttc_status gemm_f32_batched(bool a_kc, const float* A, long lda, long sa, bool b_kc, const float* B, long ldb,
+                            long sb, float* C, long ldc, long sc, int M, int N, int K, int batch, hipStream_t s) {
+  if (batch < 1 || batch > 65535) return fail(TTC_ERR_SHAPE, "GEMM batch outside [1, 65535]");
+  GemmArgs g;
+  std::memset(&g, 0, sizeof(g));
+  g.M = M;
+  g.N = N;
+  g.K = K;
+  g.lda = lda;
+  g.ldb = ldb;
+  g.ldc = ldc;
+  g.A = A;
+  g.B = B;
+  g.C = C;
+  g.alpha = 1.f;
+  g.splits = 1;
+  g.batch = batch;
+  g.sa = sa;
+  g.sb = sb;
+  g.sc = sc;
+  // vector loads need every batch member's operand 16-byte aligned too
+  g.vec_a = (lda % 4 == 0) && (sa % 4 == 0) && aligned16(A);
+  g.vec_b = (ldb % 4 == 0) && (sb % 4 == 0) && aligned16(B);
+  g.tile = gemm_tile(M, N);
+  TTC_HIP(launch_gemm(a_kc, b_kc, false, g, s));
+  return TTC_OK;
+}
+}  // namespace ttc
 
 extern "C" {
 

@@ -104,6 +104,18 @@ hipError_t launch_transfer_first(ttc_dtype dt, const void* gx, const void* gy, i
   return hipGetLastError();
 }
 
+// BF16 core -> FP32 copy (exact), for the FP32 MFMA steps.
+__global__ __launch_bounds__(256) void widen_kernel(const bf16_t* __restrict__ src, float* __restrict__ dst, long n) {
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x)
+    dst[e] = cvt<float>(src[e]);
+}
+
+hipError_t launch_widen(const void* src, float* dst, long n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(widen_kernel, dim3(grid_for(n)), dim3(256), 0, s, (const bf16_t*)src, dst, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_transfer_step(ttc_dtype dt, const void* E, const void* gx, const void* gy, long rows, int ka1,
                                 int kg1, int n, int kb, int kd, void* F, void* Eout, hipStream_t s) {
   const long tf = rows * kg1 * n * kb, te = rows * kb * kd;

@@ -36,6 +36,10 @@ struct GemmArgs {
   bool mapped;        // C element (m, n) goes to C[map(m, n)] (splits == 1)
   IdxMap map;
   GemmTile tile;
+  // batch > 1 (splits == 1, not mapped): `batch` independent products, the
+  // z-th on A + z sa, B + z sb, C + z sc
+  int batch;
+  long sa, sb, sc;
 };
 
 // dst[m * N + n] = src[map(m, n)] (the inverse of a mapped GEMM store).
@@ -82,6 +86,16 @@ struct TilePermArgs {
 };
 
 hipError_t launch_gemm(bool a_kc, bool b_kc, bool bf16, const GemmArgs& g, hipStream_t s);
+// One FP32 product C = A . B on the GEMM kernel (layouts as in GemmArgs;
+// map: the relayout store, else C row-major with ldc), split over K into
+// `slab` (at most slab_elems floats) when the output has few tiles and a
+// slab is given.  Defined with the TT layer's host code.
+ttc_status gemm_f32(bool a_kc, const float* A, long lda, bool b_kc, const float* B, long ldb, float* C, long ldc,
+                    int M, int N, int K, float* slab, size_t slab_elems, hipStream_t s, const IdxMap* map);
+// `batch` such products (no split, plain store), the z-th on A + z sa,
+// B + z sb, C + z sc.
+ttc_status gemm_f32_batched(bool a_kc, const float* A, long lda, long sa, bool b_kc, const float* B, long ldb,
+                            long sb, float* C, long ldc, long sc, int M, int N, int K, int batch, hipStream_t s);
 
 // BF16 product C (M x N, FP32, ldc) = alpha * A . B^T for BF16 A (M x K) and
 // B (N x K), both with k contiguous (lda, ldb multiples of 8, 16-byte

@@ -2,9 +2,10 @@
 b1..b2; eq. (8) once per pair; Example 1's x_n^m) against the FP64 oracle,
 through the C ABI: the junction T, the natural-order TT and the dense
 result on every block layout (middle blocks, prefix/suffix on one side,
-either tensor fully contracted), in FP64, FP32 and BF16; a middle block of
-the order-10 rank-32 pair; and Algorithm 2 from dense inputs with TT-SVD on
-the GPU (Example 1)."""
+either tensor fully contracted), in FP64 (per-entry sums), FP32 and BF16
+(MFMA products batched over the transfer's rows); a middle block of the
+order-10 rank-32 pair; transfers with more rows than one batch takes; and
+Algorithm 2 from dense inputs with TT-SVD on the GPU (Example 1)."""
 import json
 import os
 
@@ -61,6 +62,21 @@ def test_pairs_every_layout(ttc, case, dtype):
     if dtype == "bf16":
         # arithmetic only (FP32 sums of the rounded values)
         assert rel_err(T, O.transfer_junction(xs, ys, xm, ym)) <= TOL["f32"]
+
+
+@pytest.mark.parametrize("r", [255, 256])
+def test_pairs_transfer_many_rows(ttc, r):
+    """A two-pair middle block whose transfer has r^2 rows (a, g): 65025 run
+    as one batch of MFMA products per step, 65536 beyond the batch limit on
+    the per-entry path; both against the oracle's junction."""
+    sx = C.TTShape([2, 3, 3], [1, r, 4, 1])
+    sy = C.TTShape([2, 3, 3], [1, r, 3, 1])
+    x, y = _tt(5, sx.modes, sx.ranks), _tt(6, sy.modes, sy.ranks)
+    xg, xs = to_gpu(x, "f32")
+    yg, ys = to_gpu(y, "f32")
+    T = to_np(ttc.tt_contract_pairs(xg, yg, [1, 2], [1, 2], "junction"))
+    assert T.shape == (r * r, 1)
+    assert rel_err(T, O.transfer_junction(xs, ys, [1, 2], [1, 2])) <= TOL["f32"]
 
 
 def test_pairs_integer_cores_bit_exact(ttc):
