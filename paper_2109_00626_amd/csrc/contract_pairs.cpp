@@ -23,7 +23,7 @@
 namespace ttc {
 ttc_status fail(ttc_status s, const std::string& msg);
 hipError_t launch_transfer_first(ttc_dtype dt, const void* gx, const void* gy, int ka, int kg, int n, int kb,
-                                 int kd, void* E, hipStream_t s);
+                                 int kd, bool dab, void* E, hipStream_t s);
 hipError_t launch_widen(const void* src, float* dst, long n, hipStream_t s);
 hipError_t launch_transfer_step(ttc_dtype dt, const void* E, const void* gx, const void* gy, long rows, int ka1,
                                 int kg1, int n, int kb, int kd, void* F, void* Eout, hipStream_t s);
@@ -79,7 +79,7 @@ struct PairsPlan {
   // FP32 / BF16 cores: the steps after the first pair are MFMA products
   // (BF16 cores widened to FP32 first, exactly); FP64: per-entry FMA sums
   bool mfma = false;
-  long gx_max = 0, gy_max = 0;
+  long gx_max = 0, gy_max = 0, slab = 0;
   int Q = 1;              // carried bond of the natural form
   std::vector<NatCore> nat;
   std::vector<int> nmodes, nranks;
@@ -138,6 +138,8 @@ ttc_status plan_pairs(const ttc_tt* x, const ttc_tt* y, const int32_t* xm, const
       P->gx_max = std::max(P->gx_max, (long)x->ranks[mx] * x->modes[mx] * x->ranks[mx + 1]);
       P->gy_max = std::max(P->gy_max, (long)y->ranks[my] * y->modes[my] * y->ranks[my + 1]);
     }
+    // split-K partial outputs of the second product (at most four, 32 MB)
+    P->slab = std::min(4 * P->e_max, 8L << 20);
   }
   // natural form
   P->nat.clear();
@@ -209,7 +211,7 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct PairsWs {
   size_t e0 = 0, e1 = 0, f = 0, cores = 0, inner = 0, total = 0;
-  size_t gx = 0, gy = 0;  // MFMA steps on BF16 cores: the cores widened to FP32
+  size_t slab = 0, gx = 0, gy = 0;  // MFMA steps: split-K slabs; BF16 cores widened to FP32
   std::vector<size_t> core_off;
 };
 
@@ -228,9 +230,12 @@ ttc_status size_ws(const ttc_tt* x, const ttc_tt* y, const PairsPlan& P, ttc_for
     W->e0 = take(P.e_max * P.cs);
     W->e1 = take(P.e_max * P.cs);
     W->f = take(P.f_max * P.cs);
-    if (P.mfma && x->dtype == TTC_BF16) {
-      W->gx = take(P.gx_max * 4);
-      W->gy = take(P.gy_max * 4);
+    if (P.mfma) {
+      W->slab = take(P.slab * 4);
+      if (x->dtype == TTC_BF16) {
+        W->gx = take(P.gx_max * 4);
+        W->gy = take(P.gy_max * 4);
+      }
     }
     if (form == TTC_DENSE) {
       W->core_off.clear();
@@ -332,7 +337,7 @@ ttc_status tt_contract_pairs(const ttc_tt* x, const ttc_tt* y, const int32_t* xm
   void* E2 = ws + W.e1;
   void* F = ws + W.f;
   CP_HIP(launch_transfer_first(dt, x->cores[P.a1], y->cores[P.b1], P.ka, P.kg, x->modes[P.a1], x->ranks[P.a1 + 1],
-                               y->ranks[P.b1 + 1], E, s));
+                               y->ranks[P.b1 + 1], P.mfma, E, s));
   for (int l = 1; l < P.L; ++l) {
     const int mx = P.a1 + l, my = P.b1 + l;
     const int ka1 = x->ranks[mx], kg1 = y->ranks[my], nm = x->modes[mx], kb = x->ranks[mx + 1],
@@ -342,7 +347,7 @@ ttc_status tt_contract_pairs(const ttc_tt* x, const ttc_tt* y, const int32_t* xm
       std::swap(E, E2);
       continue;
     }
-    // E holds [(a, g)][a'][g'] (rows x ka1 x kg1)
+    // E holds [g'][(a, g)][a'] (kg1 x rows x ka1)
     const float* gx = reinterpret_cast<const float*>(x->cores[mx]);
     const float* gy = reinterpret_cast<const float*>(y->cores[my]);
     if (dt == TTC_BF16) {
@@ -353,14 +358,42 @@ ttc_status tt_contract_pairs(const ttc_tt* x, const ttc_tt* y, const int32_t* xm
       gx = wx;
       gy = wy;
     }
-    // per row (a, g), one product each (batched over the rows):
-    //   F[row][g'][(i, b)] = sum_a' E[row][a'][g'] Gx[a'][(i, b)]
-    //   E'[row][b][d]      = sum_{(g', i)} F[row][(g', i)][b] Gy[(g', i)][d]
-    const long fr = (long)kg1 * nm * kb;
-    CP_TRY(gemm_f32_batched(false, reinterpret_cast<const float*>(E), kg1, (long)ka1 * kg1, false, gx, (long)nm * kb,
-                            0, reinterpret_cast<float*>(F), (long)nm * kb, fr, kg1, nm * kb, ka1, (int)P.rows, s));
-    CP_TRY(gemm_f32_batched(false, reinterpret_cast<const float*>(F), kb, fr, false, gy, kd, 0,
-                            reinterpret_cast<float*>(E2), kd, (long)kb * kd, kb, kd, kg1 * nm, (int)P.rows, s));
+    const long rb = P.rows * kb;
+    // per row (a, g), batched over the rows:
+    //   F[(g', i)][(a, g)][b] = sum_a' E[g'][(a, g)][a'] Gx[a'][(i, b)]
+    // (the store places the row's g' x (i, b) block at its slots of F)
+    IdxMap fmap;
+    fmap.mr0 = 1 << 30;
+    fmap.mr1 = 1 << 30;
+    fmap.ms0 = (long)nm * rb;
+    fmap.ms1 = 0;
+    fmap.ms2 = 0;
+    fmap.nr0 = kb;
+    fmap.ns0 = 1;
+    fmap.ns1 = rb;
+    CP_TRY(gemm_f32_batched(true, reinterpret_cast<const float*>(E), P.rows * ka1, ka1, false, gx, (long)nm * kb, 0,
+                            reinterpret_cast<float*>(F), 0, kb, kg1, nm * kb, ka1, (int)P.rows, s, &fmap));
+    // then one product over all rows:
+    //   E'[d][((a, g), b)] = sum_{(g', i)} Gy[(g', i)][d] F[(g', i)][((a, g), b)]
+    // in the next pair's layout [d][(a, g)][b], or after the last pair as
+    // T[(a, g)][(b, d)]
+    float* Eo = reinterpret_cast<float*>(E2);
+    if (l < P.L - 1) {
+      CP_TRY(gemm_f32(false, gy, kd, false, reinterpret_cast<const float*>(F), rb, Eo, rb, kd, (int)rb, kg1 * nm,
+                      reinterpret_cast<float*>(ws + W.slab), (size_t)P.slab, s, nullptr));
+    } else {
+      IdxMap tmap;
+      tmap.mr0 = 1 << 30;
+      tmap.mr1 = 1 << 30;
+      tmap.ms0 = 1;
+      tmap.ms1 = 0;
+      tmap.ms2 = 0;
+      tmap.nr0 = kb;
+      tmap.ns0 = kd;
+      tmap.ns1 = (long)kb * kd;
+      CP_TRY(gemm_f32(false, gy, kd, false, reinterpret_cast<const float*>(F), rb, Eo, 0, kd, (int)rb, kg1 * nm,
+                      nullptr, 0, s, &tmap));
+    }
     std::swap(E, E2);
   }
   if (form == TTC_JUNCTION) {

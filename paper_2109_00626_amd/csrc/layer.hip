@@ -287,7 +287,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 1 : 
         for (int v = 0; v < 4; ++v) {
           const int m = m0 + am + 16 * i + 4 * lg + v;
           const int n = n0 + bn0 + 16 * j + li;
-          if (m < g.M && n < g.N) g.C[roff[i][v] + coff[j]] = g.alpha * acc[i][j][v];
+          if (m < g.M && n < g.N) g.C[(long)blockIdx.z * g.sc + roff[i][v] + coff[j]] = g.alpha * acc[i][j][v];
         }
     return;
   }

@@ -547,7 +547,8 @@ ttc_status gemm_f32(bool a_kc, const float* A, long lda, bool b_kc, const float*
 }
 
 ttc_status gemm_f32_batched(bool a_kc, const float* A, long lda, long sa, bool b_kc, const float* B, long ldb,
-                            long sb, float* C, long ldc, long sc, int M, int N, int K, int batch, hipStream_t s) {
+                            long sb, float* C, long ldc, long sc, int M, int N, int K, int batch, hipStream_t s,
+                            const IdxMap* map) {
   if (batch < 1 || batch > 65535) return fail(TTC_ERR_SHAPE, "GEMM batch outside [1, 65535]");
   GemmArgs g;
   std::memset(&g, 0, sizeof(g));
@@ -566,6 +567,10 @@ ttc_status gemm_f32_batched(bool a_kc, const float* A, long lda, long sa, bool b
   g.sa = sa;
   g.sb = sb;
   g.sc = sc;
+  if (map) {
+    g.mapped = true;
+    g.map = *map;
+  }
   // vector loads need every batch member's operand 16-byte aligned too
   g.vec_a = (lda % 4 == 0) && (sa % 4 == 0) && aligned16(A);
   g.vec_b = (ldb % 4 == 0) && (sb % 4 == 0) && aligned16(B);

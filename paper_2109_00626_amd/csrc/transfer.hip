@@ -16,17 +16,28 @@
 
 namespace ttc {
 
+// dab: E written as [d][(a, g)][b] (the layout the MFMA steps read)
+// instead of [(a, g)][b][d].
 template <typename Tin, typename Tc>
 __global__ __launch_bounds__(256) void transfer_first_kernel(const Tin* __restrict__ gx, const Tin* __restrict__ gy,
-                                                             int ka, int kg, int n, int kb, int kd,
+                                                             int ka, int kg, int n, int kb, int kd, bool dab,
                                                              Tc* __restrict__ E) {
   const long total = (long)ka * kg * kb * kd;
   for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
     long r = e;
-    const int d = (int)(r % kd);
-    r /= kd;
-    const int b = (int)(r % kb);
-    r /= kb;
+    int d, b;
+    if (dab) {
+      b = (int)(r % kb);
+      r /= kb;
+      const long rows = (long)ka * kg;
+      d = (int)(r / rows);
+      r -= (long)d * rows;
+    } else {
+      d = (int)(r % kd);
+      r /= kd;
+      b = (int)(r % kb);
+      r /= kb;
+    }
     const int g = (int)(r % kg);
     const int a = (int)(r / kg);
     const Tin* px = gx + (long)a * n * kb + b;
@@ -83,22 +94,22 @@ int grid_for(long total) { return (int)std::min<long>((total + 255) / 256, 16384
 }  // namespace
 
 hipError_t launch_transfer_first(ttc_dtype dt, const void* gx, const void* gy, int ka, int kg, int n, int kb,
-                                 int kd, void* E, hipStream_t s) {
+                                 int kd, bool dab, void* E, hipStream_t s) {
   const long total = (long)ka * kg * kb * kd;
   if (total <= 0) return hipSuccess;
   const int g = grid_for(total);
   switch (dt) {
     case TTC_F64:
       hipLaunchKernelGGL((transfer_first_kernel<double, double>), dim3(g), dim3(256), 0, s, (const double*)gx,
-                         (const double*)gy, ka, kg, n, kb, kd, (double*)E);
+                         (const double*)gy, ka, kg, n, kb, kd, dab, (double*)E);
       break;
     case TTC_F32:
       hipLaunchKernelGGL((transfer_first_kernel<float, float>), dim3(g), dim3(256), 0, s, (const float*)gx,
-                         (const float*)gy, ka, kg, n, kb, kd, (float*)E);
+                         (const float*)gy, ka, kg, n, kb, kd, dab, (float*)E);
       break;
     default:
       hipLaunchKernelGGL((transfer_first_kernel<bf16_t, float>), dim3(g), dim3(256), 0, s, (const bf16_t*)gx,
-                         (const bf16_t*)gy, ka, kg, n, kb, kd, (float*)E);
+                         (const bf16_t*)gy, ka, kg, n, kb, kd, dab, (float*)E);
       break;
   }
   return hipGetLastError();

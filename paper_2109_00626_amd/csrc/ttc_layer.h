@@ -36,8 +36,8 @@ struct GemmArgs {
   bool mapped;        // C element (m, n) goes to C[map(m, n)] (splits == 1)
   IdxMap map;
   GemmTile tile;
-  // batch > 1 (splits == 1, not mapped): `batch` independent products, the
-  // z-th on A + z sa, B + z sb, C + z sc
+  // batch > 1 (splits == 1): `batch` independent products, the z-th on
+  // A + z sa, B + z sb, C + z sc (a mapped store adds z sc to its map)
   int batch;
   long sa, sb, sc;
 };
@@ -92,10 +92,11 @@ hipError_t launch_gemm(bool a_kc, bool b_kc, bool bf16, const GemmArgs& g, hipSt
 // slab is given.  Defined with the TT layer's host code.
 ttc_status gemm_f32(bool a_kc, const float* A, long lda, bool b_kc, const float* B, long ldb, float* C, long ldc,
                     int M, int N, int K, float* slab, size_t slab_elems, hipStream_t s, const IdxMap* map);
-// `batch` such products (no split, plain store), the z-th on A + z sa,
-// B + z sb, C + z sc.
+// `batch` such products (no split), the z-th on A + z sa, B + z sb and
+// C + z sc (row-major with ldc, or through map when given).
 ttc_status gemm_f32_batched(bool a_kc, const float* A, long lda, long sa, bool b_kc, const float* B, long ldb,
-                            long sb, float* C, long ldc, long sc, int M, int N, int K, int batch, hipStream_t s);
+                            long sb, float* C, long ldc, long sc, int M, int N, int K, int batch, hipStream_t s,
+                            const IdxMap* map);
 
 // BF16 product C (M x N, FP32, ldc) = alpha * A . B^T for BF16 A (M x K) and
 // B (N x K), both with k contiguous (lda, ldb multiples of 8, 16-byte
