@@ -528,7 +528,7 @@ def main():
     elif dominant == "layer4":
         gemm_ms = fwd_ms
         ach = alg["layer4"]["fwd_flops"] / (gemm_ms * 1e-3) / 1e12
-        roof = {"bound": "mfma", "kernel": "gemm_kernel (FP32 16x16x4 MFMA), measured as the whole forward call",
+        roof = {"bound": "mfma", "kernel": "gemm_kernel (FP32 32x32x2 MFMA), measured as the whole forward call",
                 "achieved": round(ach, 2), "peak": PEAK["fp32_TFLOPs"], "unit": "TFLOP/s",
                 "frac": round(ach / PEAK["fp32_TFLOPs"], 4), "traffic": recorded_traffic("gemm_kernel"),
                 "per_launch": "2 * 8192 * 4096 * 4096 FLOP (+ 1.1 GFLOP core chain)"}

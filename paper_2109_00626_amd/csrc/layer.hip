@@ -21,10 +21,10 @@
 // through the same map, then dZ_k = dC_k Wp_k^T and dWp_k = Z_k^T dC_k.
 //
 // GEMM: 128 x 128 output tile per 256-thread workgroup, each wave a 64 x 64
-// quarter on 16x16 MFMA tiles (FP32: 16x16x4, BF16: 16x16x32 with FP32
+// quarter on MFMA tiles (FP32: 32x32x2, BF16: 16x16x32 with FP32
 // accumulation), operands staged through double-buffered LDS; thin tiles
-// (32 x 128, 128 x 32, 128 x 64) for the rank-sized products of the core
-// chain, so that a side of 32 is not padded to 128.  Global
+// (32 x 128, 128 x 32, 128 x 64; FP32 on 16x16x4) for the rank-sized
+// products of the core chain, so that a side of 32 is not padded to 128.  Global
 // operands are FP32; the BF16 variant rounds them (RNE) while staging.
 // Optional split-K writes FP32 partial slabs that a second kernel sums in a
 // fixed order (deterministic).
@@ -171,7 +171,9 @@ __host__ __device__ constexpr int tile_elems() {
 #ifndef GEMM_WPE
 #define GEMM_WPE 3
 #endif
-template <bool A_KC, bool B_KC, bool BF16, int TM, int TN>
+// W32 (FP32 128 x 128 tiles with a plain or batched store and no K
+// split): the 32x32x2 MFMA in place of 16x16x4.
+template <bool A_KC, bool B_KC, bool BF16, int TM, int TN, bool W32 = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 1 : GEMM_WPE))) void gemm_kernel(GemmArgs g) {
   extern __shared__ __align__(16) unsigned char smem[];
   typedef GemmShape<TM, TN> S;
@@ -202,6 +204,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 1 : 
   for (int i = 0; i < FI; ++i)
 #pragma unroll
     for (int j = 0; j < FJ; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // each wave's 64 x 64 block as 2 x 2 tiles of the 32x32x2 MFMA (half the
+  // MFMA instructions of 16x16x4 tiles, and the epilogue's columns 32 lanes
+  // wide): forward + backward of the order-4 layer 7.05-7.13 ms against
+  // 7.22-7.24 with 16x16x4 tiles.  The relayout-store and split-K products
+  // of the core-by-core schedule keep 16x16x4 (with 32x32x2 there, 38.7-39.0
+  // ms against 38.2 for its forward + backward; its split-K core gradients
+  // took 5.2 ms against 4.8)
+  constexpr bool M32 = W32 && !BF16 && TM == 128 && TN == 128;
+  typedef float f32x16 __attribute__((ext_vector_type(16)));
+  f32x16 acc32[2][2];
+  if constexpr (M32) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc32[i][j][r] = 0.f;
+  }
 
   f32x4 ra[LA], rb[LB];
   if (nk > 0) {
@@ -218,7 +238,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 1 : 
       load_tile<BF16, A_KC, TM>(Ag, g.lda, m0, g.M, k0, kend, g.vec_a, ra);
       load_tile<BF16, B_KC, TN>(Bg, g.ldb, n0, g.N, k0, kend, g.vec_b, rb);
     }
-    if (!BF16) {
+    if constexpr (M32) {
+      // 32x32x2 MFMA: lane l supplies A[m = l % 32][k = l / 32] and
+      // B[k = l / 32][n = l % 32]
+      const float* a_s = reinterpret_cast<const float*>(As) + buf * TA;
+      const float* b_s = reinterpret_cast<const float*>(Bs) + buf * TB;
+      const int l32 = lane & 31, h = lane >> 5;
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += 2) {
+        float av[2], bv[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) av[i] = a_s[(kk + h) * (TM + GPAD) + am + 32 * i + l32];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) bv[j] = b_s[(kk + h) * (TN + GPAD) + bn0 + 32 * j + l32];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+            acc32[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i], bv[j], acc32[i][j], 0, 0, 0);
+      }
+    } else if (!BF16) {
       const float* a_s = reinterpret_cast<const float*>(As) + buf * TA;
       const float* b_s = reinterpret_cast<const float*>(Bs) + buf * TB;
 #pragma unroll
@@ -263,6 +302,46 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 1 : 
   float* C = g.splits > 1 ? g.slab + (long)blockIdx.y * g.M * g.N : g.C + (long)blockIdx.z * g.sc;
   const long ldc = g.splits > 1 ? g.N : g.ldc;
   const float alpha = g.splits > 1 ? 1.f : g.alpha;
+  if constexpr (M32) {
+    // element r of a 32 x 32 accumulator: row 8 (r / 4) + 4 (l / 32) + r % 4,
+    // column l % 32
+    const int l32 = lane & 31, h = lane >> 5;
+    if (g.mapped) {
+      // relayout store: the column parts once, each row part once (32-bit
+      // divisions: m, n and the radices are ints)
+      long coff[2];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int n = n0 + bn0 + 32 * j + l32;
+        coff[j] = (long)(n / g.map.nr0) * g.map.ns1 + (long)(n % g.map.nr0) * g.map.ns0;
+      }
+      float* const Cz = g.C + (long)blockIdx.z * g.sc;
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int m = m0 + am + 32 * i + 8 * (r >> 2) + 4 * h + (r & 3);
+          if (m >= g.M) continue;
+          const int q = m % g.map.mr0, t = m / g.map.mr0;
+          const long ro = (long)(t / g.map.mr1) * g.map.ms2 + (long)(t % g.map.mr1) * g.map.ms1 + (long)q * g.map.ms0;
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+            if (n0 + bn0 + 32 * j + l32 < g.N) Cz[ro + coff[j]] = g.alpha * acc32[i][j][r];
+        }
+      return;
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int m = m0 + am + 32 * i + 8 * (r >> 2) + 4 * h + (r & 3);
+          const int n = n0 + bn0 + 32 * j + l32;
+          if (m < g.M && n < g.N) C[(long)m * ldc + n] = alpha * acc32[i][j][r];
+        }
+    return;
+  }
   if (g.mapped) {
     // relayout store: row and column parts of each address computed once
     long roff[FI][4], coff[FJ];
@@ -563,18 +642,18 @@ __global__ __launch_bounds__(256) void mse_final_kernel(const double* partials, 
 }
 
 // ------------------------------------------------------------------ launchers
-template <bool A_KC, bool B_KC, bool BF16, int TM, int TN>
+template <bool A_KC, bool B_KC, bool BF16, int TM, int TN, bool W32 = false>
 static hipError_t gemm_launch(const GemmArgs& g, hipStream_t s) {
   constexpr int esz = BF16 ? 2 : 4;
   const size_t lds = (size_t)2 * (tile_elems<BF16, TM>() + tile_elems<BF16, TN>()) * esz;
   static std::atomic<bool> done[kMaxDevices];
   const hipError_t e = once_per_device(done, [&] {
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm_kernel<A_KC, B_KC, BF16, TM, TN>),
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm_kernel<A_KC, B_KC, BF16, TM, TN, W32>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   });
   if (e != hipSuccess) return e;
   const int tiles = ((g.M + TM - 1) / TM) * ((g.N + TN - 1) / TN);
-  hipLaunchKernelGGL((gemm_kernel<A_KC, B_KC, BF16, TM, TN>), dim3(tiles, g.splits, g.batch > 1 ? g.batch : 1),
+  hipLaunchKernelGGL((gemm_kernel<A_KC, B_KC, BF16, TM, TN, W32>), dim3(tiles, g.splits, g.batch > 1 ? g.batch : 1),
                      dim3(256), lds, s, g);
   return hipGetLastError();
 }
@@ -585,7 +664,9 @@ static hipError_t gemm_shape(GemmTile t, const GemmArgs& g, hipStream_t s) {
     case GEMM_TILE_32x128: return gemm_launch<A_KC, B_KC, BF16, 32, 128>(g, s);
     case GEMM_TILE_128x32: return gemm_launch<A_KC, B_KC, BF16, 128, 32>(g, s);
     case GEMM_TILE_128x64: return gemm_launch<A_KC, B_KC, BF16, 128, 64>(g, s);
-    default: return gemm_launch<A_KC, B_KC, BF16, 128, 128>(g, s);
+    default:
+      if (!BF16 && !g.mapped && g.splits == 1) return gemm_launch<A_KC, B_KC, BF16, 128, 128, true>(g, s);
+      return gemm_launch<A_KC, B_KC, BF16, 128, 128>(g, s);
   }
 }
 
