@@ -248,7 +248,7 @@ __global__ __launch_bounds__(64 * MPO_WAVES) void mpo_stream_kernel(MpoArgs a, i
 // LDS row pitch of Ws (BF16 elements) for KT 32-wide K steps
 __host__ __device__ inline int mpo16_pitch(int kt) { return kt * 32 + 8; }
 
-// Workgroups of one core, LDS bytes of one chunk.
+// Groups of MPO16_WAVES consecutive vector bonds r of one core.
 __host__ __device__ inline int mpo16_groups(const MpoCore& c) { return (c.r0 + MPO16_WAVES - 1) / MPO16_WAVES; }
 
 // KT: 32-wide K steps (J <= 32 KT); RTM: r' tiles held in registers
