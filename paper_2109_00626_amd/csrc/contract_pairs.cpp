@@ -46,6 +46,10 @@ namespace {
 // Largest transfer matrix or intermediate (elements) the path takes.
 const long kMaxTransferElems = 1L << 28;
 
+// A relayout-map radix larger than any row or column index: that digit is
+// the whole index (and the next digit is zero).
+const int kWhole = 1 << 30;
+
 ttc_status check_one(const ttc_tt* t, const char* name) {
   if (!t) return fail(TTC_ERR_NULL, std::string(name) + " is NULL");
   if (t->order < 1 || t->order > TTC_MAX_ORDER) return fail(TTC_ERR_SHAPE, std::string(name) + ": order outside [1, 32]");
@@ -363,8 +367,8 @@ ttc_status tt_contract_pairs(const ttc_tt* x, const ttc_tt* y, const int32_t* xm
     //   F[(g', i)][(a, g)][b] = sum_a' E[g'][(a, g)][a'] Gx[a'][(i, b)]
     // (the store places the row's g' x (i, b) block at its slots of F)
     IdxMap fmap;
-    fmap.mr0 = 1 << 30;
-    fmap.mr1 = 1 << 30;
+    fmap.mr0 = kWhole;
+    fmap.mr1 = kWhole;
     fmap.ms0 = (long)nm * rb;
     fmap.ms1 = 0;
     fmap.ms2 = 0;
@@ -383,8 +387,8 @@ ttc_status tt_contract_pairs(const ttc_tt* x, const ttc_tt* y, const int32_t* xm
                       reinterpret_cast<float*>(ws + W.slab), (size_t)P.slab, s, nullptr));
     } else {
       IdxMap tmap;
-      tmap.mr0 = 1 << 30;
-      tmap.mr1 = 1 << 30;
+      tmap.mr0 = kWhole;
+      tmap.mr1 = kWhole;
       tmap.ms0 = 1;
       tmap.ms1 = 0;
       tmap.ms2 = 0;
