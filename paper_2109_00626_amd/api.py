@@ -385,7 +385,9 @@ def tt_contract_inner_bwd(x, y, gz, ckpt_stride: int = 0, need_x: bool = True, n
     dx_, dy_ = TTDesc(x, "x"), TTDesc(y, "y")
     dev = dx_.device
     if not torch.is_tensor(gz):
-        gz = torch.tensor(float(gz), dtype=torch.float64, device=dev)
+        # a device fill, not a host-to-device copy (which would wait for the
+        # stream's earlier work)
+        gz = torch.full((), float(gz), dtype=torch.float64, device=dev)
     gz = gz.to(device=dev, dtype=torch.float64).reshape(())
     need = c_size_t(0)
     _check(_lib.tt_contract_inner_bwd_query(dx_.ref, dy_.ref, int(ckpt_stride), byref(need)))
